@@ -1,0 +1,191 @@
+"""Pins of the oracle's network sampler (Sec. 2.2, Tables tab:params2 and
+tab:params3) and synapse storage (Sec. 3.5) -- CPU only."""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+from scipy.stats import norm
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+GOLD = json.load(open(os.path.join(HERE, "golden", "paper_values.json")))
+
+N_FULL = np.array([20683, 5834, 21915, 5479, 4850, 1065, 14395, 2948])
+V0 = [(-68.28, 5.36), (-63.16, 4.57), (-63.33, 4.74), (-63.45, 4.94), (-63.11, 4.94),
+      (-61.66, 4.55), (-66.72, 5.46), (-61.43, 4.48)]
+CONN_PRINTED = np.array([
+    [0.1009, 0.1689, 0.0437, 0.0818, 0.0323, 0.0000, 0.0076, 0.0000],
+    [0.1346, 0.1371, 0.0316, 0.0515, 0.0755, 0.0000, 0.0042, 0.0000],
+    [0.0077, 0.0059, 0.0497, 0.1350, 0.0067, 0.0003, 0.0453, 0.0000],
+    [0.0691, 0.0029, 0.0794, 0.1597, 0.0033, 0.0000, 0.1057, 0.0000],
+    [0.1004, 0.0622, 0.0505, 0.0057, 0.0831, 0.3726, 0.0204, 0.0000],
+    [0.0548, 0.0269, 0.0257, 0.0022, 0.0600, 0.3158, 0.0086, 0.0000],
+    [0.0156, 0.0066, 0.0211, 0.0166, 0.0572, 0.0197, 0.0396, 0.2252],
+    [0.0364, 0.0010, 0.0034, 0.0005, 0.0277, 0.0080, 0.0658, 0.1443]])
+
+
+def test_full_scale_counts(oracle):
+    n = oracle.pair_counts()
+    assert N_FULL.sum() == GOLD["total_neurons"]["value"]
+    g = GOLD["total_synapses"]
+    assert n.sum() == pytest.approx(g["value"], rel=g["rel_tol"])
+    # Sec. 2.2's example pair: about 2 million synapses between L23/inh and L5/exc
+    g = GOLD["l23i_to_l5e_expected"]
+    assert n[4, 1] == pytest.approx(g["value"], rel=g["rel_tol"])
+    assert n[1, 4] == pytest.approx(g["value"], rel=g["rel_tol"])
+
+
+def test_fixed_total_rule_realises_the_probability(oracle):
+    """n synapses drawn with replacement over N_pre N_post pairs connect a
+    given pair with probability 1 - (1 - 1/(N_pre N_post))^n, which must be
+    the table's p (to the rounding of n)."""
+    for scale, mode in [(1.0, 0), (0.05, 0), (0.01, 0)]:
+        cfg = oracle.Config(scale=scale, indegree_mode=mode)
+        n = oracle.pair_counts(cfg)
+        sizes = np.floor(scale * N_FULL + 0.5)
+        for b in range(8):
+            for a in range(8):
+                pairs = sizes[a] * sizes[b]
+                frac = -math.expm1(n[b, a] * math.log1p(-1.0 / pairs))
+                assert abs(frac - CONN_PRINTED[b, a]) <= 0.51 / pairs * 1.0001 + 1e-15
+
+
+def test_indegree_mode_keeps_full_scale_indegrees(oracle):
+    full = oracle.pair_counts()
+    for scale in [0.05, 0.2, 4.0]:
+        n = oracle.pair_counts(oracle.Config(scale=scale, indegree_mode=1))
+        sizes = np.floor(scale * N_FULL + 0.5)
+        np.testing.assert_allclose(n.sum(1) / sizes, full.sum(1) / N_FULL, rtol=2e-3)
+    n4 = oracle.pair_counts(oracle.Config(scale=4.0, indegree_mode=1))
+    assert n4.sum() == pytest.approx(1.2e9, rel=0.01)
+    assert np.floor(4.0 * N_FULL + 0.5).sum() == 308676
+
+
+def test_tiny_population_sizes(oracle):
+    net = oracle.Net(oracle.Config(scale=0.01))
+    off = net.pop_offsets()
+    # half-up rounding of 1 % of each population (49 for L5e's 48.5)
+    np.testing.assert_array_equal(np.diff(off), [207, 58, 219, 55, 49, 11, 144, 29])
+    assert net.N == 772
+
+
+@pytest.fixture(scope="module")
+def small(oracle):
+    cfg = oracle.Config(scale=0.05, seed=7)
+    net = oracle.Net(cfg)
+    row_ptr, post, delay, w, wq = net.csr()
+    pre = np.repeat(np.arange(net.N), np.diff(row_ptr).astype(np.int64))
+    return net, row_ptr, pre, post, delay, w, wq
+
+
+def test_storage_is_sorted_by_sender(oracle, small):
+    net, row_ptr, pre, post, delay, w, wq = small
+    assert row_ptr[0] == 0 and row_ptr[-1] == net.nsyn
+    assert np.all(np.diff(row_ptr.astype(np.int64)) >= 0)
+    assert post.max() < net.N and delay.min() >= 1 and delay.max() <= 63
+
+
+def test_pairs_land_in_their_populations(oracle, small):
+    """Senders come from the source population, receivers from the target
+    population, in the counts of the fixed-total rule; both uniform."""
+    net, row_ptr, pre, post, delay, w, wq = small
+    off = net.pop_offsets()
+    pop_pre = np.searchsorted(off, pre, side="right") - 1
+    pop_post = np.searchsorted(off, post, side="right") - 1
+    counts = np.zeros((8, 8), np.int64)
+    np.add.at(counts, (pop_post, pop_pre), 1)
+    np.testing.assert_array_equal(counts, net.pair_counts())
+    # uniform receivers inside L4e for senders in L4i: chi-square
+    m = (pop_pre == 3) & (pop_post == 2)
+    h = np.bincount(post[m] - off[2], minlength=off[3] - off[2])
+    e = m.sum() / len(h)
+    chi2 = ((h - e) ** 2 / e).sum()
+    dof = len(h) - 1
+    assert abs(chi2 - dof) < 6 * math.sqrt(2 * dof)
+
+
+def test_weight_distributions(oracle, small):
+    net, row_ptr, pre, post, delay, w, wq = small
+    wf = oracle.constants()["w_f"]
+    off = net.pop_offsets()
+    pop_pre = np.searchsorted(off, pre, side="right") - 1
+    pop_post = np.searchsorted(off, post, side="right") - 1
+    for b in range(8):
+        for a in range(8):
+            m = (pop_post == b) & (pop_pre == a)
+            if m.sum() < 200:
+                continue
+            x = w[m]
+            psp = 0.15 if a % 2 == 0 else -4.0 * 0.15
+            if (b, a) == (0, 2):
+                psp = 0.30          # the doubled L4e -> L23e pair
+            mu, sd = wf * psp, 0.1 * abs(wf * psp)
+            assert abs(x.mean() - mu) < 5 * sd / math.sqrt(len(x)), (b, a)
+            assert x.std() == pytest.approx(sd, rel=6 / math.sqrt(2 * len(x)))
+            assert np.all(np.sign(x) == np.sign(mu))
+
+
+def test_delay_distributions(oracle, small):
+    """Delays in 0.1 ms steps: Normal(1.5, 0.75) ms for excitatory and
+    Normal(0.75, 0.375) ms for inhibitory senders, rounded and clipped to
+    [1, 63] steps."""
+    net, row_ptr, pre, post, delay, w, wq = small
+    off = net.pop_offsets()
+    pop_pre = np.searchsorted(off, pre, side="right") - 1
+    for exc, (mu, sd) in [(True, (15.0, 7.5)), (False, (7.5, 3.75))]:
+        d = delay[(pop_pre % 2 == 0) == exc].astype(np.int64)
+        edges = np.arange(1, 63) + 0.5
+        cdf = norm.cdf(edges, mu, sd)
+        pmf = np.diff(np.concatenate([[0.0], cdf, [1.0]]))   # steps 1..63, tails clipped
+        h = np.bincount(d, minlength=64)[1:64]
+        e = pmf * len(d)
+        keep = e > 5
+        chi2 = ((h[keep] - e[keep]) ** 2 / e[keep]).sum()
+        dof = keep.sum() - 1
+        assert abs(chi2 - dof) < 6 * math.sqrt(2 * dof), (exc, chi2, dof)
+        assert h[~keep].sum() <= e[~keep].sum() + 6 * math.sqrt(e[~keep].sum() + 1)
+
+
+def test_initial_potentials(oracle, small):
+    net = small[0]
+    u0 = net.u0_f64()
+    off = net.pop_offsets()
+    for p in range(8):
+        x = u0[off[p]:off[p + 1]] - 65.0            # back to absolute mV
+        mu, sd = V0[p]
+        assert abs(x.mean() - mu) < 5 * sd / math.sqrt(len(x)), p
+        assert x.std() == pytest.approx(sd, rel=6 / math.sqrt(2 * len(x)))
+    np.testing.assert_array_equal(net.u0(), net.u0_f64().astype(np.float32))
+
+
+def test_weight_quantisation(oracle):
+    net = oracle.Net(oracle.Config(scale=0.02))
+    _, _, _, w, wq = net.csr()
+    assert np.all(np.abs(wq - w * 256.0) <= 0.5)
+    net = oracle.Net(oracle.Config(scale=0.02, weight_mode=oracle.W_COMPRESSED))
+    _, _, _, w2, wq2 = net.csr()
+    np.testing.assert_array_equal(w, w2)
+    assert np.all(wq2 % 8 == 0)
+    assert np.all(np.abs(wq2 // 8 - w * 32.0) <= 0.5)
+    assert np.abs(wq2 // 8).max() <= 32767
+
+
+def test_seed_changes_network(oracle):
+    a = oracle.Net(oracle.Config(scale=0.01, seed=1)).csr()
+    b = oracle.Net(oracle.Config(scale=0.01, seed=2)).csr()
+    c = oracle.Net(oracle.Config(scale=0.01, seed=1)).csr()
+    assert not np.array_equal(a[1], b[1])
+    for x, y in zip(a, c):
+        np.testing.assert_array_equal(x, y)
+
+
+def test_error_paths(oracle):
+    with pytest.raises(oracle.OracleError, match="accumulator"):
+        oracle.Net(oracle.Config(scale=0.01, g=-50000.0))
+    with pytest.raises(oracle.OracleError, match="16-bit"):
+        oracle.Net(oracle.Config(scale=0.01, g=-40.0, weight_mode=oracle.W_COMPRESSED))
+    with pytest.raises(oracle.OracleError):
+        oracle.Net(oracle.Config(scale=-1.0))
+    with pytest.raises(oracle.OracleError):
+        oracle.Net(oracle.Config(scale=0.01, conn=np.full(64, 1.5)))
