@@ -1,0 +1,235 @@
+/*
+ * snn.h -- C ABI of the MI355X (gfx950) simulator of the Potjans-Diesmann
+ * cortical microcircuit: clock-driven leaky integrate-and-fire neurons with
+ * exponential current synapses, exactly integrated at dt = 0.1 ms, push
+ * delivery of every spike into per-neuron delay ring buffers, and Poisson
+ * thalamic drive.
+ *
+ * Paper: B. A. Lindqvist, A. Podobas, "Fast Algorithms for Spiking Neural
+ * Network Simulation with FPGAs" (arXiv 2405.02019).
+ *
+ * Conventions
+ *   - Every int-returning call returns SNN_OK (0) or a negative SNN_E_* code;
+ *     snn_last_error() then describes the failure.  A failed snn_build leaves
+ *     nothing allocated.
+ *   - Host buffers are owned by the caller.  Device memory is owned by the
+ *     simulator handle: it comes from the caller's allocator callbacks when
+ *     given (e.g. the PyTorch caching allocator), otherwise from hipMalloc,
+ *     and is released by snn_destroy.
+ *   - Work is queued on one HIP stream (the caller's, or one the library
+ *     creates).  snn_step_n is asynchronous; the read calls synchronise.
+ *   - One handle must not be used from two host threads at once.
+ *   - Membrane potentials are in mV relative to the resting potential
+ *     (-65 mV): threshold 15 mV, reset 0.  Currents are in pA.  Synaptic
+ *     input is accumulated in int32 fixed point of 2^-8 pA.
+ */
+#ifndef SNN_H
+#define SNN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SNN_ABI_VERSION 1u
+
+enum snn_status {
+  SNN_OK = 0,
+  SNN_E_INVAL = -1,     /* invalid argument or configuration                  */
+  SNN_E_NOMEM = -2,     /* host or device allocation failed                   */
+  SNN_E_HIP = -3,       /* a HIP runtime call or a kernel launch failed       */
+  SNN_E_RANGE = -4,     /* a value does not fit its encoding, or a caller
+                           buffer is too small                                */
+  SNN_E_OVERFLOW = -5,  /* an int32 accumulator or the device raster could
+                           overflow                                           */
+  SNN_E_DEVICE = -6     /* the device reported a failure (a persistent kernel's
+                           bounded wait expired); the handle is unusable      */
+};
+
+/* Synapse storage formats. */
+enum snn_syn_format {
+  /* 8-byte records {int32 weight in 2^-8 pA; uint32 target << 6 | delay},
+     sorted by sender (Sec. 3.5, lst:index; the paper's 8-byte synapse). */
+  SNN_SYN_PLAIN8 = 0,
+  /* 5 bytes in three streams: uint16 target offset inside a 65,536-neuron
+     target block, int16 weight in 2^-5 pA, uint8 delay; sorted by sender,
+     then target block (the 16-bit weights of Sec. 5.1). */
+  SNN_SYN_COMPRESSED5 = 1
+};
+
+/* Step-loop engines. */
+enum snn_engine {
+  SNN_ENGINE_AUTO = 0,        /* persistent when it fits, else stepwise          */
+  SNN_ENGINE_STEPWISE = 1,    /* two kernels per step (update, then transfer)    */
+  SNN_ENGINE_PERSISTENT = 2   /* one cooperative kernel per chunk of steps, one
+                                 grid-wide barrier per step                       */
+};
+
+/* One microcircuit instance.  Defaults (snn_instance_default) are the
+ * paper's: Tables tab:params, tab:params2, tab:params3. */
+typedef struct {
+  uint64_t seed;           /* keys every random stream of the instance          */
+  double scale;            /* N_p = floor(scale * N_p(full) + 0.5), 0 < s <= 64  */
+  int32_t indegree_mode;   /* 0: connection probabilities unchanged;
+                              1: full-scale synapse counts scaled by the target
+                                 size, so in-degrees stay at full scale          */
+  int32_t count_rule;      /* 0: fixed total number n = ln(1-p)/ln(1-1/(N N'));
+                              1: expected count N N' p                           */
+  int32_t rows_are_sources;/* orientation of tab:params3; 0 = rows are targets */
+  double g;                /* inhibitory PSP = g * 0.15 mV, g <= 0 (default -4) */
+  double bg_rate_hz;       /* thalamic rate v_th (default 8 Hz)                 */
+  double psp_ext_mv;       /* thalamic PSP amplitude omega_ext (0.15 mV)        */
+  int32_t bg_const_T;      /* -1: Poisson thalamic counts; >= 0: fixed count    */
+  const double *conn;      /* NULL, or 64 probabilities [target * 8 + source]   */
+} snn_instance_cfg;
+
+typedef struct {
+  uint32_t abi_version;        /* SNN_ABI_VERSION                                */
+  uint32_t n_instances;        /* >= 1; instances evolve independently           */
+  const snn_instance_cfg *inst;
+  uint32_t syn_format;         /* enum snn_syn_format                            */
+  uint32_t engine;             /* enum snn_engine                                */
+  uint32_t chunk_steps;        /* steps per captured graph / persistent launch;
+                                  0 = 100                                         */
+  uint32_t block_size;         /* threads per block; 0 = tuned                   */
+  uint32_t grid_blocks;        /* blocks of the persistent kernel; 0 = tuned     */
+  uint64_t raster_capacity;    /* device raster entries between drains; 0 = auto */
+  int32_t host_threads;        /* threads of the network sampler; 0 = auto       */
+  int32_t use_graphs;          /* 1: replay chunks from a captured HIP graph     */
+  void *hip_stream;            /* hipStream_t; NULL = a stream of the library    */
+  void *(*dev_alloc)(size_t bytes, void *ctx); /* NULL = hipMalloc              */
+  void (*dev_free)(void *ptr, void *ctx);
+  void *alloc_ctx;
+} snn_config;
+
+typedef struct snn_net snn_net;
+
+/* Fill with defaults: one instance is NOT attached (inst = NULL). */
+void snn_config_default(snn_config *cfg);
+void snn_instance_default(snn_instance_cfg *inst);
+
+/*
+ * snn_build -- sample the network(s) on the host, upload them, precompute the
+ * propagators on the GPU and prepare the step loop.
+ *   Model: Sec. 2.2 (tables tab:params..tab:params3; w_f, eqn:p11p22, eqn:p21);
+ *   storage: Sec. 3.5 (lst:index).  Synapse counts per population pair,
+ *   Gaussian weights (sd 10 % of the mean, sign kept) and delays (rounded to
+ *   steps, clipped to [1, 63]) are drawn from counter-based Philox4x32-10
+ *   streams keyed by the instance seed; initial potentials from tab:params2.
+ * On success *out owns all device memory; on failure *out is NULL.
+ * Errors: SNN_E_INVAL (bad config), SNN_E_RANGE (a delay/weight/target that
+ * does not fit the chosen format), SNN_E_OVERFLOW (a neuron's worst-case
+ * input could overflow int32), SNN_E_NOMEM, SNN_E_HIP.
+ */
+int snn_build(const snn_config *cfg, snn_net **out);
+
+/*
+ * snn_step_n -- advance every instance by n_steps steps of dt = 0.1 ms.
+ *   One step (Sec. 3, lst:basic with lst:push / lst:push2):
+ *     for every neuron: if R == 0: x = p22 U + p21 I; x >= 15 mV => spike,
+ *     x = 0, R = 20; U = x; else U = 0, R -= 1 (eqn:mem, eqn:ref);
+ *     I = p11 I + (T w_ext + W[t mod 64]) with T ~ Poisson(v_th K dt)
+ *     (eqn:psc), then W[t mod 64] = 0;
+ *     for every spike and every synapse (j, d, w): W[(t+d) mod 64][j] += w.
+ * Asynchronous: work is queued on the handle's stream.  May synchronise to
+ * drain the device raster before it could overflow.
+ * Errors: SNN_E_HIP, SNN_E_DEVICE.
+ */
+int snn_step_n(snn_net *h, uint64_t n_steps);
+
+/*
+ * snn_read_spikes -- spikes of instance `inst` emitted in steps [t0, t1),
+ * sorted by (step, neuron id).  steps[k], ids[k] receive at most `cap`
+ * entries; *n_out is the number of spikes in the range.  Synchronises.
+ * Errors: SNN_E_INVAL, SNN_E_RANGE (cap < *n_out; nothing written),
+ * SNN_E_OVERFLOW (the device raster overflowed), SNN_E_HIP.
+ */
+int snn_read_spikes(snn_net *h, uint32_t inst, uint64_t t0, uint64_t t1, uint32_t *steps,
+                    uint32_t *ids, uint64_t cap, uint64_t *n_out);
+
+/* State of one instance.  Array pointers are caller buffers (or NULL to
+ * skip): U, I, R hold n_neurons entries; W holds 64 * n_neurons entries,
+ * row r of the ring buffer at W[r * n_neurons + i]. */
+typedef struct {
+  float *U;
+  float *I;
+  int32_t *R;
+  int32_t *W;
+  uint64_t t;              /* out: steps simulated                         */
+  uint32_t n_neurons;      /* out                                          */
+  uint64_t n_synapses;     /* out                                          */
+  uint64_t spikes;         /* out: spikes emitted                          */
+  uint64_t events;         /* out: synapses activated (sum of out-degrees) */
+  uint64_t poisson;        /* out: thalamic events (sum of T)              */
+  int64_t consumed;        /* out: ring-buffer charge read, 2^-8 pA units  */
+  float p11, p21, p22;     /* out: FP32 propagators computed on the GPU    */
+  int32_t w_ext_q;         /* out: thalamic weight, 2^-8 pA                */
+  double w_f;              /* out: PSP -> PSC factor, pA per mV            */
+} snn_state;
+
+/*
+ * snn_read_state -- copy the state of instance `inst` (after the last queued
+ * step) into the caller's buffers.  Synchronises.
+ * Errors: SNN_E_INVAL, SNN_E_HIP.
+ */
+int snn_read_state(snn_net *h, uint32_t inst, snn_state *out);
+
+/* Free all device and host memory of the handle.  NULL-safe. */
+void snn_destroy(snn_net *h);
+
+/* Message of the last failure on this handle (h == NULL: the last failure of
+ * snn_build in this thread).  Never NULL. */
+const char *snn_last_error(const snn_net *h);
+
+/* ---- launch description (for profiling and tuning reports) -------------- */
+typedef struct {
+  uint32_t engine;         /* engine in use                                  */
+  uint32_t block_size;
+  uint32_t grid_blocks;    /* persistent grid, or transfer-kernel grid      */
+  uint32_t quads_per_thread;
+  uint32_t chunk_steps;
+  uint32_t n_neurons_total;/* all instances, each padded to a multiple of 4 */
+  uint64_t n_synapses_total;
+  uint64_t device_bytes;   /* device memory held                            */
+  double build_seconds;    /* host sampling + upload                        */
+} snn_info;
+
+int snn_get_info(const snn_net *h, snn_info *out);
+
+/*
+ * snn_time_steps -- queue n_steps steps (as snn_step_n) between two HIP events
+ * recorded on the handle's stream and return the elapsed milliseconds.
+ * Synchronises.  Errors: as snn_step_n.
+ */
+int snn_time_steps(snn_net *h, uint64_t n_steps, double *elapsed_ms);
+
+/* ---- host-only network sampling (no GPU needed) --------------------------- */
+/* The network exactly as snn_build samples it, for inspection and tests:
+ * sender-sorted synapses of one instance with instance-local neuron ids. */
+typedef struct {
+  uint32_t n_neurons;
+  uint64_t n_synapses;
+  uint32_t pop_offset[9];  /* neuron ids of population p: [off[p], off[p+1]) */
+  uint64_t *row_ptr;       /* n_neurons + 1                                  */
+  uint32_t *post;          /* n_synapses: receiver                           */
+  uint8_t *delay;          /* n_synapses: steps, 1..63                       */
+  int32_t *w_q;            /* n_synapses: weight, 2^-8 pA                    */
+  float *u0;               /* n_neurons: initial potential (mV rel. E_L)     */
+} snn_host_network;
+
+/*
+ * snn_sample_network -- run the sampler of snn_build for one instance on the
+ * host (syn_format selects the weight quantisation: 2^-8 pA, or 2^-5 pA
+ * widened to 2^-8 pA) and return it; free with snn_free_network.
+ * Errors: as snn_build, minus SNN_E_HIP.
+ */
+int snn_sample_network(const snn_instance_cfg *inst, uint32_t syn_format, int32_t host_threads,
+                       snn_host_network **out);
+void snn_free_network(snn_host_network *net);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

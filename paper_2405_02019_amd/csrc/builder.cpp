@@ -1,0 +1,305 @@
+// builder.cpp -- host sampler of one microcircuit instance (Sec. 2.2) and its
+// sender-sorted synapse storage (Sec. 3.5, lst:index), written straight into
+// the device record formats.
+//
+// Each synapse k of the population pair (target b, source a) is a pure
+// function of (seed, b, a, k): two Philox4x32-10 blocks give its sender,
+// receiver, weight deviate and delay deviate.  The sampler therefore runs on
+// any number of threads in two passes over the generation order
+// (b, a, k): pass 1 counts synapses per storage segment and thread, a prefix
+// sum turns the counts into per-thread write cursors, and pass 2 regenerates
+// every synapse and writes it at its cursor.  Rows keep generation order, so
+// the result does not depend on the thread count.
+//
+// Model readings: weights Normal(mu, 0.1 |mu|) with mu = w_f * PSP,
+// PSP = 0.15 mV (excitatory sender), g * 0.15 mV (inhibitory sender), 0.30 mV
+// for L4e -> L23e; a weight that would change sign becomes 0.  Delays
+// Normal(1.5, 0.75) ms / Normal(0.75, 0.375) ms in 0.1 ms steps, rounded half
+// to even and clipped to [1, 63].  Initial potentials Normal(mean, sd) of
+// tab:params2, stored relative to -65 mV.
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <thread>
+
+#include "snn_internal.hpp"
+
+namespace snn {
+namespace {
+
+constexpr double kTwoPi = 6.283185307179586;
+
+inline double unit_open(uint32_t w) { return (double(w) + 0.5) * 0x1p-32; }
+
+// Box-Muller (cosine branch) from two 32-bit words.
+inline double gauss(uint32_t a, uint32_t b) {
+  return std::sqrt(-2.0 * std::log(unit_open(a))) * std::cos(kTwoPi * unit_open(b));
+}
+
+inline uint32_t scale_word(uint32_t w, uint32_t n) { return uint32_t((uint64_t(w) * n) >> 32); }
+
+const double kV0Mean[8] = {-68.28, -63.16, -63.33, -63.45, -63.11, -61.66, -66.72, -61.43};
+const double kV0Sd[8] = {5.36, 4.57, 4.74, 4.94, 4.94, 4.55, 5.46, 4.48};
+
+struct Pair {
+  uint64_t first;   // generation index of synapse 0 of the pair
+  uint64_t count;
+  uint32_t tgt, src;
+  uint32_t tgt0, ntgt, src0, nsrc;
+  double mu_w, sd_w, mu_d, sd_d;
+};
+
+template <class F>
+void parallel_for(int threads, F &&f) {
+  std::vector<std::thread> pool;
+  for (int t = 1; t < threads; ++t) pool.emplace_back(f, t);
+  f(0);
+  for (auto &th : pool) th.join();
+}
+
+}  // namespace
+
+int sample_instance(const snn_instance_cfg &cfg, uint32_t syn_format, int threads,
+                    HostInstance &out, std::string &err) {
+  if (!(cfg.scale > 0.0 && cfg.scale <= 64.0)) {
+    err = "scale must lie in (0, 64]";
+    return SNN_E_INVAL;
+  }
+  if (!(cfg.g <= 0.0) || !(cfg.bg_rate_hz >= 0.0) || !(cfg.psp_ext_mv >= 0.0)) {
+    err = "need g <= 0, bg_rate_hz >= 0 and psp_ext_mv >= 0";
+    return SNN_E_INVAL;
+  }
+  if (syn_format != SNN_SYN_PLAIN8 && syn_format != SNN_SYN_COMPRESSED5) {
+    err = "unknown synapse format";
+    return SNN_E_INVAL;
+  }
+  if (threads <= 0) {
+    unsigned hc = std::thread::hardware_concurrency();
+    threads = int(std::min(16u, std::max(1u, hc)));
+  }
+  out.cfg = cfg;
+  out.cfg.conn = nullptr;
+  out.conn = connectivity(cfg);
+
+  uint32_t n_pop[8];
+  population_sizes(cfg.scale, n_pop);
+  out.pop_off[0] = 0;
+  for (int p = 0; p < 8; ++p) out.pop_off[p + 1] = out.pop_off[p] + n_pop[p];
+  out.n = out.pop_off[8];
+  if (out.n == 0) {
+    err = "the scale leaves no neurons";
+    return SNN_E_INVAL;
+  }
+  if (out.n >= (1u << 26)) {
+    err = "more than 2^26 neurons per instance";
+    return SNN_E_RANGE;
+  }
+  int rc = pair_counts(cfg, out.conn, n_pop, out.pair_count, err);
+  if (rc) return rc;
+
+  const ModelConstants mc = model_constants();
+  out.w_f = mc.w_f;
+  out.w_ext = mc.w_f * cfg.psp_ext_mv;
+  const double wq_ext = std::nearbyint(out.w_ext * 256.0);
+  if (!(std::fabs(wq_ext) < 2147483647.0)) {
+    err = "thalamic weight does not fit int32 fixed point";
+    return SNN_E_RANGE;
+  }
+  out.w_ext_q = int32_t(wq_ext);
+
+  // Thalamic drive: Poisson with mean v_th K dt (dt = 1e-4 s), or a constant.
+  uint32_t tmax = 0;
+  for (int p = 0; p < 8; ++p) {
+    if (cfg.bg_const_T >= 0) {
+      if (cfg.bg_const_T > kMaxPoisson) {
+        err = "constant thalamic count above 64";
+        return SNN_E_INVAL;
+      }
+      for (int k = 0; k < cfg.bg_const_T; ++k) out.thr[p][k] = 0;
+      out.thr_len[p] = uint32_t(cfg.bg_const_T);
+    } else {
+      const double lam = (cfg.bg_rate_hz * double(kKext[p])) * 1e-4;
+      rc = poisson_thresholds(lam, out.thr[p], kMaxPoisson, &out.thr_len[p], err);
+      if (rc) return rc;
+    }
+    tmax = std::max(tmax, out.thr_len[p]);
+  }
+
+  // Initial membrane potentials.
+  out.u0.assign(out.n, 0.0f);
+  for (int p = 0; p < 8; ++p)
+    for (uint32_t i = out.pop_off[p]; i < out.pop_off[p + 1]; ++i) {
+      const Philox4 r = philox4x32_10(i, 0, 0, kStreamInitialV, uint32_t(cfg.seed),
+                                      uint32_t(cfg.seed >> 32));
+      const double v = kV0Mean[p] + kV0Sd[p] * gauss(r.v[0], r.v[1]);
+      out.u0[i] = float(v - (-65.0));
+    }
+
+  // Population pairs in generation order (target-major).
+  std::vector<Pair> pairs;
+  uint64_t S = 0;
+  const double w_f = mc.w_f;
+  for (uint32_t b = 0; b < 8; ++b)
+    for (uint32_t a = 0; a < 8; ++a) {
+      const uint64_t c = out.pair_count[b * 8 + a];
+      if (!c) continue;
+      Pair pr{};
+      pr.first = S;
+      pr.count = c;
+      pr.tgt = b;
+      pr.src = a;
+      pr.tgt0 = out.pop_off[b];
+      pr.ntgt = n_pop[b];
+      pr.src0 = out.pop_off[a];
+      pr.nsrc = n_pop[a];
+      const bool exc = (a % 2) == 0;
+      double psp = exc ? 0.15 : cfg.g * 0.15;
+      if (b == 0 && a == 2) psp = 2.0 * 0.15;
+      pr.mu_w = psp * w_f;
+      pr.sd_w = 0.1 * std::fabs(pr.mu_w);
+      pr.mu_d = exc ? 15.0 : 7.5;
+      pr.sd_d = exc ? 7.5 : 3.75;
+      pairs.push_back(pr);
+      S += c;
+    }
+  out.nsyn = S;
+
+  const bool comp = syn_format == SNN_SYN_COMPRESSED5;
+  const uint32_t nwin = comp ? ((out.n + (1u << kTargetBlockBits) - 1) >> kTargetBlockBits) : 1u;
+  out.nwin = nwin;
+  const uint64_t nseg = uint64_t(out.n) * nwin;
+  const uint32_t key0 = uint32_t(cfg.seed), key1 = uint32_t(cfg.seed >> 32);
+
+  // Thread ranges over the generation order.
+  const int P = int(std::max<uint64_t>(1, std::min<uint64_t>(uint64_t(threads), S ? S : 1)));
+  std::vector<uint64_t> lo(P + 1);
+  for (int t = 0; t <= P; ++t) lo[t] = S / P * t + std::min<uint64_t>(S % P, t);
+
+  auto locate = [&](uint64_t e) {  // pair containing generation index e
+    size_t i = std::upper_bound(pairs.begin(), pairs.end(), e,
+                                [](uint64_t v, const Pair &p) { return v < p.first; }) -
+               pairs.begin();
+    return i - 1;
+  };
+
+  // Pass 1: per-thread segment counts.
+  std::vector<std::vector<uint64_t>> cur(P);
+  parallel_for(P, [&](int t) {
+    std::vector<uint64_t> &h = cur[t];
+    h.assign(nseg, 0);
+    if (lo[t] == lo[t + 1]) return;
+    size_t pi = locate(lo[t]);
+    for (uint64_t e = lo[t]; e < lo[t + 1]; ++e) {
+      while (e >= pairs[pi].first + pairs[pi].count) ++pi;
+      const Pair &pr = pairs[pi];
+      const uint32_t k = uint32_t(e - pr.first);
+      const uint32_t code = 2u * (pr.tgt * 8u + pr.src);
+      const Philox4 r = philox4x32_10(k, code, 0, kStreamSynapse, key0, key1);
+      const uint32_t pre = pr.src0 + scale_word(r.v[0], pr.nsrc);
+      const uint32_t post = pr.tgt0 + scale_word(r.v[1], pr.ntgt);
+      h[uint64_t(pre) * nwin + (comp ? (post >> kTargetBlockBits) : 0u)] += 1;
+    }
+  });
+
+  // Segment pointers and per-thread cursors (segment-major, thread-minor).
+  out.seg_ptr.assign(nseg + 1, 0);
+  {
+    uint64_t run = 0;
+    for (uint64_t s = 0; s < nseg; ++s) {
+      out.seg_ptr[s] = run;
+      for (int t = 0; t < P; ++t) {
+        const uint64_t c = cur[t][s];
+        cur[t][s] = run;
+        run += c;
+      }
+    }
+    out.seg_ptr[nseg] = run;
+  }
+
+  if (comp) {
+    out.rec8.clear();
+    out.tgt16.assign(S, 0);
+    out.w16.assign(S, 0);
+    out.d8.assign(S, 0);
+  } else {
+    out.rec8.assign(S, 0);
+  }
+
+  // Pass 2: regenerate and place; per-thread worst-case input per receiver.
+  std::atomic<int> bad{0};
+  std::vector<std::vector<int64_t>> insum(P);
+  parallel_for(P, [&](int t) {
+    std::vector<uint64_t> &c = cur[t];
+    std::vector<int64_t> &in = insum[t];
+    in.assign(out.n, 0);
+    if (lo[t] == lo[t + 1]) return;
+    size_t pi = locate(lo[t]);
+    for (uint64_t e = lo[t]; e < lo[t + 1]; ++e) {
+      while (e >= pairs[pi].first + pairs[pi].count) ++pi;
+      const Pair &pr = pairs[pi];
+      const uint32_t k = uint32_t(e - pr.first);
+      const uint32_t code = 2u * (pr.tgt * 8u + pr.src);
+      const Philox4 r = philox4x32_10(k, code, 0, kStreamSynapse, key0, key1);
+      const Philox4 s = philox4x32_10(k, code + 1u, 0, kStreamSynapse, key0, key1);
+      const uint32_t pre = pr.src0 + scale_word(r.v[0], pr.nsrc);
+      const uint32_t post = pr.tgt0 + scale_word(r.v[1], pr.ntgt);
+      double w = pr.mu_w + pr.sd_w * gauss(r.v[2], r.v[3]);
+      if (pr.mu_w > 0.0 && w < 0.0) w = 0.0;
+      if (pr.mu_w < 0.0 && w > 0.0) w = 0.0;
+      const double dr = std::nearbyint(pr.mu_d + pr.sd_d * gauss(s.v[0], s.v[1]));
+      const uint32_t d = dr < 1.0 ? 1u : (dr > double(kMaxDelay) ? uint32_t(kMaxDelay) : uint32_t(dr));
+      const uint64_t seg = uint64_t(pre) * nwin + (comp ? (post >> kTargetBlockBits) : 0u);
+      const uint64_t pos = c[seg]++;
+      int32_t wq;
+      if (comp) {
+        const double q = std::nearbyint(w * 32.0);
+        if (!(q >= -32768.0 && q <= 32767.0)) {
+          bad.store(2);
+          continue;
+        }
+        out.tgt16[pos] = uint16_t(post & ((1u << kTargetBlockBits) - 1u));
+        out.w16[pos] = int16_t(q);
+        out.d8[pos] = uint8_t(d);
+        wq = int32_t(q) * 8;
+      } else {
+        const double q = std::nearbyint(w * 256.0);
+        if (!(std::fabs(q) < 2147483647.0)) {
+          bad.store(1);
+          continue;
+        }
+        wq = int32_t(q);
+        out.rec8[pos] = uint64_t(uint32_t(wq)) | (uint64_t((post << 6) | d) << 32);
+      }
+      in[post] += std::llabs(int64_t(wq));
+    }
+  });
+  if (bad.load() == 2) {
+    err = "a weight does not fit the 16-bit compressed encoding";
+    return SNN_E_RANGE;
+  }
+  if (bad.load() == 1) {
+    err = "a weight does not fit int32 fixed point";
+    return SNN_E_RANGE;
+  }
+  // Worst case of one step's input: every synapse onto a neuron plus the
+  // longest thalamic count must stay inside int32.
+  int64_t worst = 0;
+  for (uint32_t i = 0; i < out.n; ++i) {
+    int64_t s = 0;
+    for (int t = 0; t < P; ++t) s += insum[t][i];
+    worst = std::max(worst, s);
+  }
+  worst += int64_t(tmax) * std::llabs(int64_t(out.w_ext_q));
+  if (worst >= 2147483647LL) {
+    char b[128];
+    std::snprintf(b, sizeof b, "worst-case input %lld exceeds the int32 accumulator",
+                  (long long)worst);
+    err = b;
+    return SNN_E_OVERFLOW;
+  }
+  return SNN_OK;
+}
+
+}  // namespace snn

@@ -1,0 +1,611 @@
+// runtime.hip -- the C ABI of include/snn.h: network upload, device memory
+// (caller allocator or hipMalloc), the HIP stream, captured step chunks, raster
+// drains and state readback.
+#include <algorithm>
+#include <chrono>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "engine.hpp"
+
+using namespace snn;
+
+namespace {
+thread_local std::string g_build_error;
+
+struct InstMeta {
+  uint32_t n = 0, gbase = 0, npad = 0;
+  uint32_t pop_off[9] = {};
+  uint64_t nsyn = 0;
+  double w_f = 0.0;
+  int32_t w_ext_q = 0;
+};
+}  // namespace
+
+struct snn_net {
+  snn_config cfg{};
+  std::vector<InstMeta> im;
+  DeviceNet d;
+  LaunchShape shape;
+  uint32_t engine = SNN_ENGINE_STEPWISE;
+  uint32_t chunk = 100;
+  uint64_t n_real = 0;              // neurons without padding
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  std::vector<void *> allocs;
+  size_t device_bytes = 0;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+  std::vector<uint64_t> raster;     // drained, sorted by (step, global id)
+  uint64_t t = 0;
+  uint64_t pending = 0;             // worst-case raster entries since the last drain
+  bool overflowed = false;
+  bool dead = false;
+  std::string err;
+  double build_seconds = 0.0;
+};
+
+namespace {
+
+int fail(snn_net *h, int code, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  std::vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  if (h)
+    h->err = buf;
+  else
+    g_build_error = buf;
+  return code;
+}
+
+#define HIP_OK(h, expr)                                                                    \
+  do {                                                                                     \
+    hipError_t e_ = (expr);                                                                \
+    if (e_ != hipSuccess) return fail((h), SNN_E_HIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+int dalloc(snn_net *h, void **p, size_t bytes) {
+  bytes = std::max<size_t>(256, (bytes + 255) & ~size_t(255));
+  void *q = nullptr;
+  if (h->cfg.dev_alloc) {
+    q = h->cfg.dev_alloc(bytes, h->cfg.alloc_ctx);
+  } else if (hipMalloc(&q, bytes) != hipSuccess) {
+    q = nullptr;
+  }
+  if (!q) return fail(h, SNN_E_NOMEM, "device allocation of %zu bytes failed", bytes);
+  h->allocs.push_back(q);
+  h->device_bytes += bytes;
+  *p = q;
+  return SNN_OK;
+}
+
+template <class T>
+int dalloc_n(snn_net *h, T **p, size_t n) {
+  void *q = nullptr;
+  int rc = dalloc(h, &q, n * sizeof(T));
+  *p = static_cast<T *>(q);
+  return rc;
+}
+
+void release(snn_net *h) {
+  if (!h) return;
+  if (h->stream) (void)hipStreamSynchronize(h->stream);
+  if (h->graph_exec) (void)hipGraphExecDestroy(h->graph_exec);
+  if (h->graph) (void)hipGraphDestroy(h->graph);
+  for (void *p : h->allocs) {
+    if (h->cfg.dev_free)
+      h->cfg.dev_free(p, h->cfg.alloc_ctx);
+    else
+      (void)hipFree(p);
+  }
+  h->allocs.clear();
+  if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
+  h->stream = nullptr;
+}
+
+// Copy the device raster to the host store and reset it.
+int drain(snn_net *h) {
+  HIP_OK(h, hipStreamSynchronize(h->stream));
+  Control c{};
+  HIP_OK(h, hipMemcpy(&c, h->d.ctl, sizeof c, hipMemcpyDeviceToHost));
+  if (c.error) {
+    h->dead = true;
+    return fail(h, SNN_E_DEVICE, "a bounded device wait expired (code %u)", c.error);
+  }
+  if (c.overflow) h->overflowed = true;
+  const uint64_t m = std::min<uint64_t>(c.raster_n, h->d.raster_cap);
+  if (m) {
+    const size_t old = h->raster.size();
+    h->raster.resize(old + m);
+    HIP_OK(h, hipMemcpy(h->raster.data() + old, h->d.raster, m * sizeof(uint64_t),
+                        hipMemcpyDeviceToHost));
+    std::sort(h->raster.begin() + old, h->raster.end());
+  }
+  HIP_OK(h, launch_reset_raster(h->d, h->stream));
+  h->pending = 0;
+  return SNN_OK;
+}
+
+uint64_t spike_bound(const snn_net *h, uint64_t steps) {
+  // A neuron spikes at most once per 21 steps (20 refractory steps).
+  return h->n_real * ((steps + kRefSteps) / (kRefSteps + 1));
+}
+
+int queue_steps(snn_net *h, uint32_t n) {
+  if (h->graph_exec && n == h->chunk) {
+    HIP_OK(h, hipGraphLaunch(h->graph_exec, h->stream));
+    return SNN_OK;
+  }
+  HIP_OK(h, launch_stepwise(h->d, h->shape, n, h->stream));
+  return SNN_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void snn_instance_default(snn_instance_cfg *c) {
+  if (!c) return;
+  std::memset(c, 0, sizeof *c);
+  c->seed = 1;
+  c->scale = 1.0;
+  c->indegree_mode = 0;
+  c->count_rule = 0;
+  c->rows_are_sources = 0;
+  c->g = -4.0;
+  c->bg_rate_hz = 8.0;
+  c->psp_ext_mv = 0.15;
+  c->bg_const_T = -1;
+  c->conn = nullptr;
+}
+
+void snn_config_default(snn_config *c) {
+  if (!c) return;
+  std::memset(c, 0, sizeof *c);
+  c->abi_version = SNN_ABI_VERSION;
+  c->n_instances = 1;
+  c->inst = nullptr;
+  c->syn_format = SNN_SYN_PLAIN8;
+  c->engine = SNN_ENGINE_AUTO;
+  c->chunk_steps = 100;
+  c->use_graphs = 1;
+}
+
+const char *snn_last_error(const snn_net *h) {
+  return h ? h->err.c_str() : g_build_error.c_str();
+}
+
+void snn_destroy(snn_net *h) {
+  if (!h) return;
+  release(h);
+  delete h;
+}
+
+int snn_build(const snn_config *cfg, snn_net **out) {
+  if (!out) return fail(nullptr, SNN_E_INVAL, "out is NULL");
+  *out = nullptr;
+  if (!cfg) return fail(nullptr, SNN_E_INVAL, "cfg is NULL");
+  if (cfg->abi_version != SNN_ABI_VERSION)
+    return fail(nullptr, SNN_E_INVAL, "ABI version %u, library has %u", cfg->abi_version,
+                SNN_ABI_VERSION);
+  if (cfg->n_instances < 1 || cfg->n_instances > kMaxInstances || !cfg->inst)
+    return fail(nullptr, SNN_E_INVAL, "need 1..%u instances", kMaxInstances);
+  if (cfg->syn_format > SNN_SYN_COMPRESSED5)
+    return fail(nullptr, SNN_E_INVAL, "unknown synapse format %u", cfg->syn_format);
+  if (cfg->engine > SNN_ENGINE_PERSISTENT)
+    return fail(nullptr, SNN_E_INVAL, "unknown engine %u", cfg->engine);
+  const auto t_start = std::chrono::steady_clock::now();
+
+  snn_net *h = new snn_net();
+  h->cfg = *cfg;
+  h->cfg.inst = nullptr;
+  h->chunk = cfg->chunk_steps ? cfg->chunk_steps : 100;
+  auto bail = [&](int rc) {
+    g_build_error = h->err;
+    snn_destroy(h);
+    return rc;
+  };
+
+  // ---- sample every instance on the host ----
+  const uint32_t ni = cfg->n_instances;
+  std::vector<HostInstance> hi(ni);
+  h->im.resize(ni);
+  uint32_t gbase = 0, nwin_max = 1;
+  uint64_t nseg_tot = 0, nsyn_tot = 0, nthr = 0;
+  for (uint32_t k = 0; k < ni; ++k) {
+    std::string e;
+    int rc = sample_instance(cfg->inst[k], cfg->syn_format, cfg->host_threads, hi[k], e);
+    if (rc) {
+      fail(h, rc, "instance %u: %s", k, e.c_str());
+      return bail(rc);
+    }
+    InstMeta &m = h->im[k];
+    m.n = hi[k].n;
+    m.npad = (m.n + kInstAlign - 1) / kInstAlign * kInstAlign;
+    m.gbase = gbase;
+    std::memcpy(m.pop_off, hi[k].pop_off, sizeof m.pop_off);
+    m.nsyn = hi[k].nsyn;
+    m.w_f = hi[k].w_f;
+    m.w_ext_q = hi[k].w_ext_q;
+    if (uint64_t(gbase) + m.npad >= (1ull << 26)) {
+      fail(h, SNN_E_RANGE, "more than 2^26 neurons in total");
+      return bail(SNN_E_RANGE);
+    }
+    gbase += m.npad;
+    nwin_max = std::max(nwin_max, hi[k].nwin);
+    nseg_tot += uint64_t(m.n) * hi[k].nwin;
+    nsyn_tot += m.nsyn;
+    for (int p = 0; p < 8; ++p) nthr += hi[k].thr_len[p];
+    h->n_real += m.n;
+  }
+  DeviceNet &d = h->d;
+  d.n_inst = ni;
+  d.ntot = gbase;
+  d.nquads = gbase / 4;
+  d.nwin_max = nwin_max;
+  d.syn_format = cfg->syn_format;
+
+  // ---- stream ----
+  if (cfg->hip_stream) {
+    h->stream = static_cast<hipStream_t>(cfg->hip_stream);
+  } else {
+    if (hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking) != hipSuccess) {
+      fail(h, SNN_E_HIP, "hipStreamCreate failed");
+      return bail(SNN_E_HIP);
+    }
+    h->own_stream = true;
+  }
+
+  // ---- device memory ----
+  InstDev *d_inst;
+  uint32_t *d_qinfo, *d_thr;
+  uint64_t *d_seg, *d_rec8 = nullptr;
+  uint16_t *d_tgt16 = nullptr;
+  int16_t *d_w16 = nullptr;
+  uint8_t *d_d8 = nullptr;
+  const bool comp = cfg->syn_format == SNN_SYN_COMPRESSED5;
+  uint64_t cap = cfg->raster_capacity;
+  if (!cap) cap = std::max<uint64_t>(uint64_t(1) << 20, uint64_t(256) * d.ntot);
+  cap = std::max<uint64_t>(cap, 2 * h->n_real + 64);
+  d.raster_cap = cap;
+  int rc = SNN_OK;
+#define ALLOC(ptr, n)                           \
+  do {                                          \
+    rc = dalloc_n(h, &(ptr), (n));              \
+    if (rc) return bail(rc);                    \
+  } while (0)
+  ALLOC(d_inst, ni);
+  ALLOC(d_qinfo, d.nquads);
+  ALLOC(d_thr, std::max<uint64_t>(1, nthr));
+  ALLOC(d.U, d.ntot);
+  ALLOC(d.I, d.ntot);
+  ALLOC(d.R4, d.nquads);
+  ALLOC(d.W, size_t(kRing) * d.ntot);
+  ALLOC(d_seg, nseg_tot + 1);
+  if (comp) {
+    ALLOC(d_tgt16, std::max<uint64_t>(1, nsyn_tot));
+    ALLOC(d_w16, std::max<uint64_t>(1, nsyn_tot));
+    ALLOC(d_d8, std::max<uint64_t>(1, nsyn_tot));
+  } else {
+    ALLOC(d_rec8, std::max<uint64_t>(1, nsyn_tot));
+  }
+  ALLOC(d.spk_list, 2 * size_t(d.ntot));
+  ALLOC(d.raster, cap);
+  ALLOC(d.wave_ctr, 4 * size_t(d.nquads / 64));
+  ALLOC(d.events, ni);
+  ALLOC(d.consts, 1);
+  ALLOC(d.ctl, 1);
+#undef ALLOC
+
+  // ---- host staging and upload ----
+  std::vector<InstDev> hinst(ni);
+  std::vector<uint32_t> qinfo(d.nquads, 0);
+  std::vector<uint32_t> thr;
+  std::vector<float> u0(d.ntot, 0.0f);
+  std::vector<uint64_t> seg;
+  seg.reserve(nseg_tot + 1);
+  uint64_t syn_base = 0;
+  for (uint32_t k = 0; k < ni; ++k) {
+    const HostInstance &x = hi[k];
+    const InstMeta &m = h->im[k];
+    InstDev &v = hinst[k];
+    std::memset(&v, 0, sizeof v);
+    v.seed = x.cfg.seed;
+    v.gbase = m.gbase;
+    v.n = m.n;
+    v.npad = m.npad;
+    v.w_ext_q = x.w_ext_q;
+    std::memcpy(v.pop_off, x.pop_off, sizeof v.pop_off);
+    for (int p = 0; p < 8; ++p) {
+      v.thr_off[p] = uint32_t(thr.size());
+      v.thr_len[p] = x.thr_len[p];
+      thr.insert(thr.end(), x.thr[p], x.thr[p] + x.thr_len[p]);
+    }
+    v.seg_base = uint32_t(seg.size());
+    v.nwin = x.nwin;
+    for (uint32_t lq = 0; lq < m.npad / 4; ++lq) qinfo[m.gbase / 4 + lq] = (k << 24) | lq;
+    std::copy(x.u0.begin(), x.u0.end(), u0.begin() + m.gbase);
+    for (uint64_t s = 0; s + 1 < x.seg_ptr.size(); ++s) seg.push_back(syn_base + x.seg_ptr[s]);
+    syn_base += x.nsyn;
+  }
+  seg.push_back(syn_base);
+  if (seg.size() >= (uint64_t(1) << 32)) {
+    fail(h, SNN_E_RANGE, "too many storage segments");
+    return bail(SNN_E_RANGE);
+  }
+#define UPLOAD(dst, src, bytes)                                                     \
+  do {                                                                              \
+    if ((bytes) && hipMemcpy((dst), (src), (bytes), hipMemcpyHostToDevice) != hipSuccess) { \
+      fail(h, SNN_E_HIP, "upload of %s failed", #src);                              \
+      return bail(SNN_E_HIP);                                                       \
+    }                                                                               \
+  } while (0)
+  UPLOAD(d_inst, hinst.data(), ni * sizeof(InstDev));
+  UPLOAD(d_qinfo, qinfo.data(), qinfo.size() * sizeof(uint32_t));
+  UPLOAD(d_thr, thr.data(), thr.size() * sizeof(uint32_t));
+  UPLOAD(d.U, u0.data(), u0.size() * sizeof(float));
+  UPLOAD(d_seg, seg.data(), seg.size() * sizeof(uint64_t));
+  syn_base = 0;
+  for (uint32_t k = 0; k < ni; ++k) {
+    HostInstance &x = hi[k];
+    if (comp) {
+      UPLOAD(d_tgt16 + syn_base, x.tgt16.data(), x.nsyn * sizeof(uint16_t));
+      UPLOAD(d_w16 + syn_base, x.w16.data(), x.nsyn * sizeof(int16_t));
+      UPLOAD(d_d8 + syn_base, x.d8.data(), x.nsyn * sizeof(uint8_t));
+    } else {
+      if (h->im[k].gbase) {  // targets become global ids
+        const uint64_t add = uint64_t(h->im[k].gbase) << 38;
+        for (auto &r : x.rec8) r += add;
+      }
+      UPLOAD(d_rec8 + syn_base, x.rec8.data(), x.nsyn * sizeof(uint64_t));
+    }
+    syn_base += x.nsyn;
+    x = HostInstance();  // release host copies early
+  }
+#undef UPLOAD
+  d.inst = d_inst;
+  d.qinfo = d_qinfo;
+  d.thr = d_thr;
+  d.seg_ptr = d_seg;
+  d.rec8 = d_rec8;
+  d.tgt16 = d_tgt16;
+  d.w16 = d_w16;
+  d.d8 = d_d8;
+  if (hipMemset(d.I, 0, d.ntot * sizeof(float)) != hipSuccess ||
+      hipMemset(d.R4, 0, d.nquads * sizeof(uint32_t)) != hipSuccess ||
+      hipMemset(d.W, 0, size_t(kRing) * d.ntot * sizeof(int32_t)) != hipSuccess ||
+      hipMemset(d.spk_list, 0, 2 * size_t(d.ntot) * sizeof(uint32_t)) != hipSuccess ||
+      hipMemset(d.wave_ctr, 0, 4 * size_t(d.nquads / 64) * sizeof(int64_t)) != hipSuccess ||
+      hipMemset(d.events, 0, ni * sizeof(uint64_t)) != hipSuccess ||
+      hipMemset(d.ctl, 0, sizeof(Control)) != hipSuccess) {
+    fail(h, SNN_E_HIP, "device memset failed");
+    return bail(SNN_E_HIP);
+  }
+  if (launch_propagators(d, h->stream) != hipSuccess ||
+      hipStreamSynchronize(h->stream) != hipSuccess) {
+    fail(h, SNN_E_HIP, "propagator kernel failed");
+    return bail(SNN_E_HIP);
+  }
+
+  // ---- engine ----
+  h->engine = SNN_ENGINE_STEPWISE;
+  h->shape.block = 256;
+  h->shape.scatter_blocks = cfg->grid_blocks ? cfg->grid_blocks : 1024;
+  if (cfg->use_graphs) {
+    if (hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+      fail(h, SNN_E_HIP, "stream capture failed to start");
+      return bail(SNN_E_HIP);
+    }
+    hipError_t le = launch_stepwise(d, h->shape, h->chunk, h->stream);
+    hipError_t ce = hipStreamEndCapture(h->stream, &h->graph);
+    if (le != hipSuccess || ce != hipSuccess ||
+        hipGraphInstantiate(&h->graph_exec, h->graph, nullptr, nullptr, 0) != hipSuccess) {
+      fail(h, SNN_E_HIP, "graph capture of a %u-step chunk failed", h->chunk);
+      return bail(SNN_E_HIP);
+    }
+  }
+  h->build_seconds =
+      std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+  *out = h;
+  return SNN_OK;
+}
+
+int snn_step_n(snn_net *h, uint64_t n_steps) {
+  if (!h) return fail(nullptr, SNN_E_INVAL, "handle is NULL");
+  if (h->dead) return fail(h, SNN_E_DEVICE, "the handle is unusable after a device failure");
+  while (n_steps) {
+    uint64_t piece = std::min<uint64_t>(n_steps, h->chunk);
+    while (piece > 1 && spike_bound(h, piece) > h->d.raster_cap) piece /= 2;
+    if (h->pending + spike_bound(h, piece) > h->d.raster_cap) {
+      int rc = drain(h);
+      if (rc) return rc;
+    }
+    int rc = queue_steps(h, uint32_t(piece));
+    if (rc) return rc;
+    h->pending += spike_bound(h, piece);
+    h->t += piece;
+    n_steps -= piece;
+  }
+  return SNN_OK;
+}
+
+int snn_read_spikes(snn_net *h, uint32_t inst, uint64_t t0, uint64_t t1, uint32_t *steps,
+                    uint32_t *ids, uint64_t cap, uint64_t *n_out) {
+  if (!h || !n_out) return fail(h, SNN_E_INVAL, "NULL argument");
+  if (inst >= h->im.size()) return fail(h, SNN_E_INVAL, "instance %u out of range", inst);
+  int rc = drain(h);
+  if (rc) return rc;
+  if (h->overflowed) return fail(h, SNN_E_OVERFLOW, "the device raster overflowed");
+  const InstMeta &m = h->im[inst];
+  t0 = std::min<uint64_t>(t0, 0xFFFFFFFFull);
+  t1 = std::min<uint64_t>(t1, 0x100000000ull);
+  auto lo = std::lower_bound(h->raster.begin(), h->raster.end(), t0 << 32);
+  auto hi = t1 >= 0x100000000ull ? h->raster.end()
+                                 : std::lower_bound(h->raster.begin(), h->raster.end(), t1 << 32);
+  uint64_t cnt = 0;
+  for (auto it = lo; it < hi; ++it) {
+    const uint32_t g = uint32_t(*it);
+    cnt += (g >= m.gbase && g < m.gbase + m.n);
+  }
+  *n_out = cnt;
+  if (!steps && !ids) return SNN_OK;
+  if (cnt > cap) return fail(h, SNN_E_RANGE, "%llu spikes, buffer holds %llu",
+                             (unsigned long long)cnt, (unsigned long long)cap);
+  uint64_t k = 0;
+  for (auto it = lo; it < hi; ++it) {
+    const uint32_t g = uint32_t(*it);
+    if (g < m.gbase || g >= m.gbase + m.n) continue;
+    if (steps) steps[k] = uint32_t(*it >> 32);
+    if (ids) ids[k] = g - m.gbase;
+    ++k;
+  }
+  return SNN_OK;
+}
+
+int snn_read_state(snn_net *h, uint32_t inst, snn_state *out) {
+  if (!h || !out) return fail(h, SNN_E_INVAL, "NULL argument");
+  if (inst >= h->im.size()) return fail(h, SNN_E_INVAL, "instance %u out of range", inst);
+  HIP_OK(h, hipStreamSynchronize(h->stream));
+  const InstMeta &m = h->im[inst];
+  const DeviceNet &d = h->d;
+  if (out->U) HIP_OK(h, hipMemcpy(out->U, d.U + m.gbase, m.n * sizeof(float), hipMemcpyDeviceToHost));
+  if (out->I) HIP_OK(h, hipMemcpy(out->I, d.I + m.gbase, m.n * sizeof(float), hipMemcpyDeviceToHost));
+  if (out->R) {
+    std::vector<uint32_t> r4(m.npad / 4);
+    HIP_OK(h, hipMemcpy(r4.data(), d.R4 + m.gbase / 4, r4.size() * sizeof(uint32_t),
+                        hipMemcpyDeviceToHost));
+    for (uint32_t i = 0; i < m.n; ++i) out->R[i] = int32_t((r4[i / 4] >> (8 * (i % 4))) & 0xFFu);
+  }
+  if (out->W) {
+    HIP_OK(h, hipMemcpy2D(out->W, m.n * sizeof(int32_t), d.W + m.gbase, size_t(d.ntot) * sizeof(int32_t),
+                          m.n * sizeof(int32_t), kRing, hipMemcpyDeviceToHost));
+  }
+  std::vector<int64_t> wc(4 * size_t(m.npad / 256));
+  HIP_OK(h, hipMemcpy(wc.data(), d.wave_ctr + 4 * size_t(m.gbase / 256), wc.size() * sizeof(int64_t),
+                      hipMemcpyDeviceToHost));
+  int64_t sp = 0, po = 0, co = 0;
+  for (size_t w = 0; w < wc.size() / 4; ++w) {
+    sp += wc[4 * w];
+    po += wc[4 * w + 1];
+    co += wc[4 * w + 2];
+  }
+  uint64_t ev = 0;
+  HIP_OK(h, hipMemcpy(&ev, d.events + inst, sizeof ev, hipMemcpyDeviceToHost));
+  DevConsts kc{};
+  HIP_OK(h, hipMemcpy(&kc, d.consts, sizeof kc, hipMemcpyDeviceToHost));
+  out->t = h->t;
+  out->n_neurons = m.n;
+  out->n_synapses = m.nsyn;
+  out->spikes = uint64_t(sp);
+  out->events = ev;
+  out->poisson = uint64_t(po);
+  out->consumed = co;
+  out->p11 = kc.p11;
+  out->p21 = kc.p21;
+  out->p22 = kc.p22;
+  out->w_ext_q = m.w_ext_q;
+  out->w_f = m.w_f;
+  return SNN_OK;
+}
+
+int snn_get_info(const snn_net *h, snn_info *out) {
+  if (!h || !out) return SNN_E_INVAL;
+  std::memset(out, 0, sizeof *out);
+  out->engine = h->engine;
+  out->block_size = h->shape.block;
+  out->grid_blocks = h->engine == SNN_ENGINE_PERSISTENT ? h->shape.grid : h->shape.scatter_blocks;
+  out->quads_per_thread = h->shape.qpt;
+  out->chunk_steps = h->chunk;
+  out->n_neurons_total = h->d.ntot;
+  uint64_t s = 0;
+  for (const auto &m : h->im) s += m.nsyn;
+  out->n_synapses_total = s;
+  out->device_bytes = h->device_bytes;
+  out->build_seconds = h->build_seconds;
+  return SNN_OK;
+}
+
+int snn_time_steps(snn_net *h, uint64_t n_steps, double *elapsed_ms) {
+  if (!h || !elapsed_ms) return fail(h, SNN_E_INVAL, "NULL argument");
+  hipEvent_t a, b;
+  HIP_OK(h, hipEventCreate(&a));
+  HIP_OK(h, hipEventCreate(&b));
+  HIP_OK(h, hipEventRecord(a, h->stream));
+  int rc = snn_step_n(h, n_steps);
+  if (rc) {
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    return rc;
+  }
+  HIP_OK(h, hipEventRecord(b, h->stream));
+  HIP_OK(h, hipEventSynchronize(b));
+  float ms = 0.0f;
+  HIP_OK(h, hipEventElapsedTime(&ms, a, b));
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  *elapsed_ms = ms;
+  return SNN_OK;
+}
+
+int snn_sample_network(const snn_instance_cfg *inst, uint32_t syn_format, int32_t host_threads,
+                       snn_host_network **out) {
+  if (!inst || !out) return fail(nullptr, SNN_E_INVAL, "NULL argument");
+  *out = nullptr;
+  HostInstance x;
+  std::string e;
+  int rc = sample_instance(*inst, syn_format, host_threads, x, e);
+  if (rc) return fail(nullptr, rc, "%s", e.c_str());
+  snn_host_network *n = static_cast<snn_host_network *>(std::calloc(1, sizeof(snn_host_network)));
+  if (!n) return fail(nullptr, SNN_E_NOMEM, "host allocation failed");
+  n->n_neurons = x.n;
+  n->n_synapses = x.nsyn;
+  std::memcpy(n->pop_offset, x.pop_off, sizeof n->pop_offset);
+  n->row_ptr = static_cast<uint64_t *>(std::malloc((x.n + 1) * sizeof(uint64_t)));
+  n->post = static_cast<uint32_t *>(std::malloc(std::max<uint64_t>(1, x.nsyn) * sizeof(uint32_t)));
+  n->delay = static_cast<uint8_t *>(std::malloc(std::max<uint64_t>(1, x.nsyn)));
+  n->w_q = static_cast<int32_t *>(std::malloc(std::max<uint64_t>(1, x.nsyn) * sizeof(int32_t)));
+  n->u0 = static_cast<float *>(std::malloc(x.n * sizeof(float)));
+  if (!n->row_ptr || !n->post || !n->delay || !n->w_q || !n->u0) {
+    snn_free_network(n);
+    return fail(nullptr, SNN_E_NOMEM, "host allocation failed");
+  }
+  for (uint32_t i = 0; i <= x.n; ++i) n->row_ptr[i] = x.seg_ptr[uint64_t(i) * x.nwin];
+  std::memcpy(n->u0, x.u0.data(), x.n * sizeof(float));
+  const bool comp = syn_format == SNN_SYN_COMPRESSED5;
+  for (uint32_t i = 0; i < x.n; ++i)
+    for (uint32_t w = 0; w < x.nwin; ++w) {
+      const uint64_t s = uint64_t(i) * x.nwin + w;
+      for (uint64_t e2 = x.seg_ptr[s]; e2 < x.seg_ptr[s + 1]; ++e2) {
+        if (comp) {
+          n->post[e2] = (w << kTargetBlockBits) + x.tgt16[e2];
+          n->delay[e2] = x.d8[e2];
+          n->w_q[e2] = int32_t(x.w16[e2]) * 8;
+        } else {
+          const uint32_t hiw = uint32_t(x.rec8[e2] >> 32);
+          n->post[e2] = hiw >> 6;
+          n->delay[e2] = uint8_t(hiw & 63u);
+          n->w_q[e2] = int32_t(uint32_t(x.rec8[e2]));
+        }
+      }
+    }
+  *out = n;
+  return SNN_OK;
+}
+
+void snn_free_network(snn_host_network *n) {
+  if (!n) return;
+  std::free(n->row_ptr);
+  std::free(n->post);
+  std::free(n->delay);
+  std::free(n->w_q);
+  std::free(n->u0);
+  std::free(n);
+}
+
+}  // extern "C"

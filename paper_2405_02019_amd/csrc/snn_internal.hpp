@@ -1,0 +1,126 @@
+// snn_internal.hpp -- definitions shared by the simulator library's own
+// translation units (host sampler, runtime and HIP kernels).
+#pragma once
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/snn.h"
+
+#if defined(__HIPCC__)
+#define SNN_HD __host__ __device__
+#else
+#define SNN_HD
+#endif
+
+namespace snn {
+
+// Ring buffer of 64 rows: delays are 1..63 steps (Sec. 3.2).
+constexpr int kRing = 64;
+constexpr int kMaxDelay = kRing - 1;
+// Refractory period 2 ms = 20 steps of 0.1 ms; threshold -50 mV = 15 mV above
+// the resting potential (tab:params).
+constexpr int kRefSteps = 20;
+constexpr float kTheta = 15.0f;
+// Neurons of an instance are padded to whole waves of quads (64 x 4), so a
+// wavefront never mixes two instances.
+constexpr uint32_t kInstAlign = 256;
+constexpr uint32_t kTargetBlockBits = 16;  // compressed targets: 16-bit offsets
+constexpr int kMaxPoisson = 64;            // longest thalamic table
+constexpr uint32_t kMaxInstances = 256;
+
+// Philox counter word 3 names the random stream.
+constexpr uint32_t kStreamSynapse = 1;   // (k, 2 * pair + half, 0)
+constexpr uint32_t kStreamInitialV = 2;  // (neuron, 0, 0)
+constexpr uint32_t kStreamThalamic = 3;  // (neuron / 4, step lo, step hi)
+
+// Philox4x32-10 of Salmon et al. (SC'11): ten rounds of two 32x32->64-bit
+// multiplications with the Philox constants, XOR with the round key, and a
+// word permutation; the key advances by the golden-ratio Weyl increments.
+struct Philox4 {
+  uint32_t v[4];
+};
+
+SNN_HD inline Philox4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                    uint32_t k0, uint32_t k1) {
+#if defined(__HIPCC__)
+#pragma unroll
+#endif
+  for (int r = 0; r < 10; ++r) {
+    const uint64_t a = uint64_t(0xD2511F53u) * c0;
+    const uint64_t b = uint64_t(0xCD9E8D57u) * c2;
+    const uint32_t n0 = uint32_t(b >> 32) ^ c1 ^ k0;
+    const uint32_t n2 = uint32_t(a >> 32) ^ c3 ^ k1;
+    c1 = uint32_t(b);
+    c3 = uint32_t(a);
+    c0 = n0;
+    c2 = n2;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  return Philox4{{c0, c1, c2, c3}};
+}
+
+// Per-instance table the kernels read (device memory, uniform per wave).
+struct InstDev {
+  uint64_t seed;
+  uint32_t gbase;        // first global neuron id (multiple of kInstAlign)
+  uint32_t n;            // neurons
+  uint32_t npad;         // neurons rounded up to kInstAlign
+  int32_t w_ext_q;       // thalamic weight, 2^-8 pA
+  uint32_t pop_off[9];   // local population boundaries
+  uint32_t thr_off[8];   // first threshold of each population in the table
+  uint32_t thr_len[8];
+  uint32_t seg_base;     // first segment of the instance
+  uint32_t nwin;         // segments per neuron (target blocks; 1 for plain)
+};
+
+// FP32 propagators, computed in FP64 on the device (eqn:p11p22, eqn:p21).
+struct DevConsts {
+  float p11, p22, p21, pad;
+  double p11d, p22d, p21d, padd;
+};
+
+// Host side of one instance after sampling.
+struct HostInstance {
+  snn_instance_cfg cfg{};
+  std::vector<double> conn;          // 64, [target][source]
+  uint32_t n = 0;
+  uint32_t pop_off[9] = {};
+  uint64_t pair_count[64] = {};      // [target * 8 + source]
+  uint64_t nsyn = 0;
+  double w_f = 0.0, w_ext = 0.0;
+  int32_t w_ext_q = 0;
+  uint32_t thr[8][kMaxPoisson] = {};
+  uint32_t thr_len[8] = {};
+  std::vector<float> u0;
+  // Storage: segments [n * nwin + 1] into the record streams.
+  uint32_t nwin = 1;
+  std::vector<uint64_t> seg_ptr;
+  std::vector<uint64_t> rec8;        // plain: w_q | (target << 6 | delay) << 32
+  std::vector<uint16_t> tgt16;       // compressed streams
+  std::vector<int16_t> w16;
+  std::vector<uint8_t> d8;
+};
+
+// Model (model.cpp).
+struct ModelConstants {
+  double w_f, p11, p22, p21;
+};
+ModelConstants model_constants();
+int pair_counts(const snn_instance_cfg &cfg, const std::vector<double> &conn,
+                const uint32_t n_pop[8], uint64_t out[64], std::string &err);
+int poisson_thresholds(double lam, uint32_t *thr, uint32_t cap, uint32_t *len, std::string &err);
+void population_sizes(double scale, uint32_t n_pop[8]);
+std::vector<double> connectivity(const snn_instance_cfg &cfg);
+extern const uint32_t kPopFull[8];
+extern const uint32_t kKext[8];
+
+// Sampler (builder.cpp).  Targets are instance-local ids; the runtime offsets
+// plain records by the instance's first global id when it uploads them.
+int sample_instance(const snn_instance_cfg &cfg, uint32_t syn_format, int threads,
+                    HostInstance &out, std::string &err);
+
+}  // namespace snn

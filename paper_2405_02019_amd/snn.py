@@ -1,0 +1,307 @@
+"""Python binding of libsnn.so (include/snn.h): argument marshalling only.
+
+Every step of the simulation runs in the library's HIP kernels.  PyTorch
+provides the device memory (the caching allocator, through the library's
+allocator callbacks) and the HIP stream the work is queued on.  There is no
+fallback: if the library is not built, or no GPU is present, the calls raise.
+"""
+import ctypes as C
+import os
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsnn.so")
+
+SYN_PLAIN8 = 0
+SYN_COMPRESSED5 = 1
+ENGINE_AUTO = 0
+ENGINE_STEPWISE = 1
+ENGINE_PERSISTENT = 2
+ABI_VERSION = 1
+
+SNN_OK = 0
+ERRORS = {-1: "SNN_E_INVAL", -2: "SNN_E_NOMEM", -3: "SNN_E_HIP", -4: "SNN_E_RANGE",
+          -5: "SNN_E_OVERFLOW", -6: "SNN_E_DEVICE"}
+
+
+class SnnError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class _Inst(C.Structure):
+    _fields_ = [("seed", C.c_uint64), ("scale", C.c_double), ("indegree_mode", C.c_int32),
+                ("count_rule", C.c_int32), ("rows_are_sources", C.c_int32), ("g", C.c_double),
+                ("bg_rate_hz", C.c_double), ("psp_ext_mv", C.c_double), ("bg_const_T", C.c_int32),
+                ("conn", C.POINTER(C.c_double))]
+
+
+_ALLOC = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+_FREE = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+
+
+class _Cfg(C.Structure):
+    _fields_ = [("abi_version", C.c_uint32), ("n_instances", C.c_uint32),
+                ("inst", C.POINTER(_Inst)), ("syn_format", C.c_uint32), ("engine", C.c_uint32),
+                ("chunk_steps", C.c_uint32), ("block_size", C.c_uint32),
+                ("grid_blocks", C.c_uint32), ("raster_capacity", C.c_uint64),
+                ("host_threads", C.c_int32), ("use_graphs", C.c_int32),
+                ("hip_stream", C.c_void_p), ("dev_alloc", _ALLOC), ("dev_free", _FREE),
+                ("alloc_ctx", C.c_void_p)]
+
+
+class _State(C.Structure):
+    _fields_ = [("U", C.POINTER(C.c_float)), ("I", C.POINTER(C.c_float)),
+                ("R", C.POINTER(C.c_int32)), ("W", C.POINTER(C.c_int32)), ("t", C.c_uint64),
+                ("n_neurons", C.c_uint32), ("n_synapses", C.c_uint64), ("spikes", C.c_uint64),
+                ("events", C.c_uint64), ("poisson", C.c_uint64), ("consumed", C.c_int64),
+                ("p11", C.c_float), ("p21", C.c_float), ("p22", C.c_float),
+                ("w_ext_q", C.c_int32), ("w_f", C.c_double)]
+
+
+class _Info(C.Structure):
+    _fields_ = [("engine", C.c_uint32), ("block_size", C.c_uint32), ("grid_blocks", C.c_uint32),
+                ("quads_per_thread", C.c_uint32), ("chunk_steps", C.c_uint32),
+                ("n_neurons_total", C.c_uint32), ("n_synapses_total", C.c_uint64),
+                ("device_bytes", C.c_uint64), ("build_seconds", C.c_double)]
+
+
+class _HostNet(C.Structure):
+    _fields_ = [("n_neurons", C.c_uint32), ("n_synapses", C.c_uint64),
+                ("pop_offset", C.c_uint32 * 9), ("row_ptr", C.POINTER(C.c_uint64)),
+                ("post", C.POINTER(C.c_uint32)), ("delay", C.POINTER(C.c_uint8)),
+                ("w_q", C.POINTER(C.c_int32)), ("u0", C.POINTER(C.c_float))]
+
+
+# Every function the header declares, with its C signature.
+SIGNATURES = {
+    "snn_config_default": (None, [C.POINTER(_Cfg)]),
+    "snn_instance_default": (None, [C.POINTER(_Inst)]),
+    "snn_build": (C.c_int, [C.POINTER(_Cfg), C.POINTER(C.c_void_p)]),
+    "snn_step_n": (C.c_int, [C.c_void_p, C.c_uint64]),
+    "snn_read_spikes": (C.c_int, [C.c_void_p, C.c_uint32, C.c_uint64, C.c_uint64,
+                                  C.POINTER(C.c_uint32), C.POINTER(C.c_uint32), C.c_uint64,
+                                  C.POINTER(C.c_uint64)]),
+    "snn_read_state": (C.c_int, [C.c_void_p, C.c_uint32, C.POINTER(_State)]),
+    "snn_destroy": (None, [C.c_void_p]),
+    "snn_last_error": (C.c_char_p, [C.c_void_p]),
+    "snn_get_info": (C.c_int, [C.c_void_p, C.POINTER(_Info)]),
+    "snn_time_steps": (C.c_int, [C.c_void_p, C.c_uint64, C.POINTER(C.c_double)]),
+    "snn_sample_network": (C.c_int, [C.POINTER(_Inst), C.c_uint32, C.c_int32,
+                                     C.POINTER(C.POINTER(_HostNet))]),
+    "snn_free_network": (None, [C.POINTER(_HostNet)]),
+}
+
+_lib = None
+
+
+def lib():
+    """Load libsnn.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                               "(or python paper_2405_02019_amd/build_lib.py)")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(rc, h=None):
+    if rc != SNN_OK:
+        raise SnnError(rc, lib().snn_last_error(h).decode())
+
+
+@dataclass
+class Instance:
+    """One microcircuit instance; defaults are the paper's tables."""
+    seed: int = 1
+    scale: float = 1.0
+    indegree_mode: int = 0
+    count_rule: int = 0
+    rows_are_sources: int = 0
+    g: float = -4.0
+    bg_rate_hz: float = 8.0
+    psp_ext_mv: float = 0.15
+    bg_const_T: int = -1
+    conn: Optional[Sequence[float]] = None
+
+    def fill(self, s: _Inst, keep: list):
+        s.seed = int(self.seed)
+        s.scale = float(self.scale)
+        s.indegree_mode = int(self.indegree_mode)
+        s.count_rule = int(self.count_rule)
+        s.rows_are_sources = int(self.rows_are_sources)
+        s.g = float(self.g)
+        s.bg_rate_hz = float(self.bg_rate_hz)
+        s.psp_ext_mv = float(self.psp_ext_mv)
+        s.bg_const_T = int(self.bg_const_T)
+        if self.conn is not None:
+            arr = (C.c_double * 64)(*[float(x) for x in np.asarray(self.conn).ravel()])
+            keep.append(arr)
+            s.conn = C.cast(arr, C.POINTER(C.c_double))
+        else:
+            s.conn = None
+
+
+def _syn_format(fmt):
+    if isinstance(fmt, str):
+        return {"plain": SYN_PLAIN8, "compressed": SYN_COMPRESSED5}[fmt]
+    return int(fmt)
+
+
+def _engine(e):
+    if isinstance(e, str):
+        return {"auto": ENGINE_AUTO, "stepwise": ENGINE_STEPWISE, "persistent": ENGINE_PERSISTENT}[e]
+    return int(e)
+
+
+class Simulator:
+    """A handle of the C ABI: one or more instances simulated together."""
+
+    def __init__(self, instances, syn_format="plain", engine="auto", chunk_steps=100,
+                 use_graphs=True, block_size=0, grid_blocks=0, raster_capacity=0,
+                 host_threads=0, device=0):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU: the simulator runs only on an MI355X (gfx950)")
+        if isinstance(instances, Instance):
+            instances = [instances]
+        self.instances = list(instances)
+        self._torch = torch
+        self.device = torch.device("cuda", device)
+        self._blocks = {}
+        self.stream = torch.cuda.Stream(device=self.device)
+
+        def _alloc(size, ctx):
+            try:
+                t = torch.empty(int(size), dtype=torch.uint8, device=self.device)
+            except Exception:  # noqa: BLE001 -- report as a NULL allocation
+                return None
+            p = t.data_ptr()
+            self._blocks[p] = t
+            return p
+
+        def _free(ptr, ctx):
+            self._blocks.pop(ptr, None)
+
+        self._alloc_cb = _ALLOC(_alloc)
+        self._free_cb = _FREE(_free)
+        keep = []
+        arr = (_Inst * len(self.instances))()
+        for k, inst in enumerate(self.instances):
+            inst.fill(arr[k], keep)
+        cfg = _Cfg()
+        lib().snn_config_default(C.byref(cfg))
+        cfg.n_instances = len(self.instances)
+        cfg.inst = C.cast(arr, C.POINTER(_Inst))
+        cfg.syn_format = _syn_format(syn_format)
+        cfg.engine = _engine(engine)
+        cfg.chunk_steps = int(chunk_steps)
+        cfg.use_graphs = 1 if use_graphs else 0
+        cfg.block_size = int(block_size)
+        cfg.grid_blocks = int(grid_blocks)
+        cfg.raster_capacity = int(raster_capacity)
+        cfg.host_threads = int(host_threads)
+        cfg.hip_stream = C.c_void_p(self.stream.cuda_stream)
+        cfg.dev_alloc = self._alloc_cb
+        cfg.dev_free = self._free_cb
+        h = C.c_void_p()
+        with torch.cuda.device(self.device):
+            _check(lib().snn_build(C.byref(cfg), C.byref(h)))
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().snn_destroy(self.h)
+            self.h = None
+            self._blocks.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # noqa: BLE001 -- interpreter shutdown
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def step(self, n_steps):
+        _check(lib().snn_step_n(self.h, int(n_steps)), self.h)
+        return self
+
+    def time_steps(self, n_steps):
+        ms = C.c_double()
+        _check(lib().snn_time_steps(self.h, int(n_steps), C.byref(ms)), self.h)
+        return ms.value
+
+    def spikes(self, inst=0, t0=0, t1=2**32):
+        n = C.c_uint64()
+        _check(lib().snn_read_spikes(self.h, inst, t0, t1, None, None, 0, C.byref(n)), self.h)
+        steps = np.zeros(n.value, np.uint32)
+        ids = np.zeros(n.value, np.uint32)
+        _check(lib().snn_read_spikes(self.h, inst, t0, t1,
+                                     steps.ctypes.data_as(C.POINTER(C.c_uint32)),
+                                     ids.ctypes.data_as(C.POINTER(C.c_uint32)), n.value,
+                                     C.byref(n)), self.h)
+        return steps, ids
+
+    def state(self, inst=0, ring=False):
+        st = _State()
+        _check(lib().snn_read_state(self.h, inst, C.byref(st)), self.h)
+        n = st.n_neurons
+        U = np.zeros(n, np.float32)
+        I = np.zeros(n, np.float32)
+        R = np.zeros(n, np.int32)
+        W = np.zeros((64, n), np.int32) if ring else None
+        st.U = U.ctypes.data_as(C.POINTER(C.c_float))
+        st.I = I.ctypes.data_as(C.POINTER(C.c_float))
+        st.R = R.ctypes.data_as(C.POINTER(C.c_int32))
+        st.W = W.ctypes.data_as(C.POINTER(C.c_int32)) if ring else None
+        _check(lib().snn_read_state(self.h, inst, C.byref(st)), self.h)
+        out = {f: getattr(st, f) for f, _ in _State._fields_ if f not in ("U", "I", "R", "W")}
+        out.update(U=U, I=I, R=R)
+        if ring:
+            out["W"] = W
+        return out
+
+    def info(self):
+        inf = _Info()
+        _check(lib().snn_get_info(self.h, C.byref(inf)), self.h)
+        return {f: getattr(inf, f) for f, _ in _Info._fields_}
+
+
+def sample_network(instance: Instance, syn_format="plain", host_threads=0):
+    """The network snn_build would upload, sampled on the host (no GPU)."""
+    keep = []
+    s = _Inst()
+    instance.fill(s, keep)
+    p = C.POINTER(_HostNet)()
+    _check(lib().snn_sample_network(C.byref(s), _syn_format(syn_format), int(host_threads),
+                                    C.byref(p)))
+    try:
+        net = p.contents
+        n, m = net.n_neurons, net.n_synapses
+
+        def arr(ptr, k, dt):
+            if k == 0:
+                return np.zeros(0, dt)
+            return np.ctypeslib.as_array(ptr, shape=(int(k),)).astype(dt, copy=True)
+
+        return {"n": n, "nsyn": m, "pop_offset": np.array(net.pop_offset[:], np.int64),
+                "row_ptr": arr(net.row_ptr, n + 1, np.uint64), "post": arr(net.post, m, np.uint32),
+                "delay": arr(net.delay, m, np.uint8), "w_q": arr(net.w_q, m, np.int32),
+                "u0": arr(net.u0, n, np.float32)}
+    finally:
+        lib().snn_free_network(p)

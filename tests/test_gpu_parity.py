@@ -1,0 +1,142 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle, element
+by element.  The plain and compressed paths must reproduce the oracle's spike
+rasters, membrane potentials, currents, refractory counters, ring buffers and
+counters bit for bit: every FP32 operation is separately rounded on both sides
+and all synaptic input is an exact int32 sum."""
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[gpu-parity]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def P():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible")
+    import paper_2405_02019_amd as P
+    P.lib()
+    return P
+
+
+def oracle_cfg(oracle, inst, wmode):
+    return oracle.Config(seed=inst.seed, scale=inst.scale, indegree_mode=inst.indegree_mode,
+                         count_rule=inst.count_rule, rows_are_sources=inst.rows_are_sources,
+                         g=inst.g, bg_rate_hz=inst.bg_rate_hz, psp_ext_mv=inst.psp_ext_mv,
+                         bg_const_T=inst.bg_const_T, conn=inst.conn, weight_mode=wmode)
+
+
+def run_oracle(oracle, inst, wmode, steps):
+    net = oracle.Net(oracle_cfg(oracle, inst, wmode))
+    sim = oracle.Sim(net).run(steps)
+    return net, sim
+
+
+def assert_parity(sim, k, net, osim, ring=True):
+    gs, gi = sim.spikes(k)
+    os_, oi = osim.raster()
+    assert len(gs) == len(os_), (len(gs), len(os_))
+    np.testing.assert_array_equal(gs, os_)
+    np.testing.assert_array_equal(gi, oi)
+    st = sim.state(k, ring=ring)
+    ost = osim.state()
+    assert st["t"] == ost["t"]
+    np.testing.assert_array_equal(st["U"], ost["U"])
+    np.testing.assert_array_equal(st["I"], ost["I"])
+    np.testing.assert_array_equal(st["R"], ost["R"])
+    if ring:
+        np.testing.assert_array_equal(st["W"].astype(np.int64), ost["W"])
+    c = osim.counters()
+    assert st["spikes"] == c["spikes"]
+    assert st["events"] == c["events"]
+    assert st["poisson"] == c["poisson"]
+    assert st["consumed"] == c["consumed"]
+    return len(gs)
+
+
+def test_propagators_on_gpu(P, oracle):
+    with P.Simulator(P.Instance(scale=0.01)) as sim:
+        st = sim.state()
+    k = oracle.constants()
+    assert st["p11"] == np.float32(k["p11f"])
+    assert st["p22"] == np.float32(k["p22f"])
+    assert st["p21"] == np.float32(k["p21f"])
+    assert st["w_ext_q"] == k["w_ext_q"] and st["w_f"] == k["w_f"]
+
+
+@pytest.mark.parametrize("engine", ["stepwise"])
+@pytest.mark.parametrize("fmt,wmode", [("plain", 0), ("compressed", 1)])
+def test_tiny_circuit_bit_exact(P, oracle, engine, fmt, wmode):
+    """1 % circuit (772 neurons), 0.1 s of biological time in ragged pieces
+    (1, 99, 100, 63, 65, 672 steps) across graph-chunk boundaries."""
+    inst = P.Instance(scale=0.01, seed=1)
+    say("tiny", engine, fmt)
+    with P.Simulator(inst, syn_format=fmt, engine=engine) as sim:
+        for n in [1, 99, 100, 63, 65, 672]:
+            sim.step(n)
+        net, osim = run_oracle(oracle, inst, wmode, 1000)
+        n = assert_parity(sim, 0, net, osim)
+    assert n > 5000
+
+
+def test_tiny_without_graphs_and_odd_chunks(P, oracle):
+    inst = P.Instance(scale=0.01, seed=2)
+    for kw in [dict(use_graphs=False), dict(chunk_steps=7)]:
+        say("tiny", kw)
+        with P.Simulator(inst, **kw) as sim:
+            sim.step(300)
+            sim.step(33)
+            net, osim = run_oracle(oracle, inst, 0, 333)
+            assert_parity(sim, 0, net, osim)
+
+
+def test_degenerate_drives(P, oracle):
+    """No synapses and no thalamic input; then a constant count of one
+    thalamic spike per step at a sub-threshold amplitude; then no drive at
+    all on the full tables."""
+    cases = [P.Instance(scale=0.01, seed=3, bg_rate_hz=0.0, conn=np.zeros(64)),
+             P.Instance(scale=0.01, seed=3, bg_const_T=1, psp_ext_mv=0.07),
+             P.Instance(scale=0.01, seed=4, bg_rate_hz=0.0)]
+    for inst in cases:
+        say("degenerate", inst)
+        with P.Simulator(inst) as sim:
+            sim.step(250)
+            net, osim = run_oracle(oracle, inst, 0, 250)
+            assert_parity(sim, 0, net, osim)
+
+
+def test_batched_instances_each_bit_exact(P, oracle):
+    """Several independent instances of uneven scale, seed, g and thalamic
+    rate in one handle: each matches its own oracle run."""
+    insts = [P.Instance(scale=0.01, seed=11),
+             P.Instance(scale=0.023, seed=12, g=-5.0, bg_rate_hz=9.0),
+             P.Instance(scale=0.013, seed=13, g=-3.5, bg_rate_hz=6.5, indegree_mode=1),
+             P.Instance(scale=0.002, seed=14)]
+    for fmt, wmode in [("plain", 0), ("compressed", 1)]:
+        say("batch", fmt)
+        with P.Simulator(insts, syn_format=fmt) as sim:
+            sim.step(400)
+            for k, inst in enumerate(insts):
+                net, osim = run_oracle(oracle, inst, wmode, 400)
+                assert_parity(sim, k, net, osim)
+
+
+def test_full_scale_window_bit_exact(P, oracle):
+    """Full-scale microcircuit (77,169 neurons, 2.99e8 synapses): the first
+    300 steps match the oracle spike for spike, with the whole state."""
+    inst = P.Instance(scale=1.0, seed=1)
+    say("full scale: building GPU network")
+    with P.Simulator(inst) as sim:
+        sim.step(300)
+        say("full scale: building oracle network")
+        net, osim = run_oracle(oracle, inst, 0, 300)
+        say("full scale: comparing")
+        n = assert_parity(sim, 0, net, osim)
+        say("full scale spikes", n)
