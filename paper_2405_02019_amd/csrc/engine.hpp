@@ -8,16 +8,30 @@
 
 namespace snn {
 
+// LDS copies of the thalamic tables (thresholds, and per (instance,
+// population) offset and length): used when the batch's tables fit.
+constexpr uint32_t kThrLds = 8192;
+constexpr uint32_t kMetaLds = 512;
+
 // Small control block in device memory.
 struct Control {
   uint64_t t_base;        // first step of the next launch
   uint64_t raster_n;      // raster entries written since the last drain
-  uint32_t spk_cnt[2];    // senders of step t live in slot t & 1
+  uint32_t spk_cnt[2];    // stepwise: senders of step t live in slot t & 1
   uint32_t overflow;      // raster capacity exceeded
   uint32_t error;         // a bounded wait of the persistent kernel expired
-  uint64_t barrier;       // persistent kernel: arrivals
-  uint64_t exit_count;    // persistent kernel: blocks that have left
+  uint64_t barrier;       // persistent kernel: arrivals at the grid barrier
+  uint64_t exit_count;    // persistent kernel: blocks that have finished
+  uint32_t lcnt[4];       // persistent: segment-list lengths, 3 rotating slots
   uint64_t pad[2];
+};
+
+// One storage segment of a sender, as published by the persistent engine for
+// the transfer phase of the next iteration.
+struct SegEntry {
+  uint64_t start;         // first record
+  uint32_t len;           // records
+  uint32_t tbase;         // global id of the segment's target block
 };
 
 struct DeviceNet {
@@ -28,7 +42,11 @@ struct DeviceNet {
   uint32_t syn_format = SNN_SYN_PLAIN8;
   const InstDev *inst = nullptr;
   const uint32_t *qinfo = nullptr;  // per quad: instance << 24 | local quad
-  const uint32_t *thr = nullptr;
+  const uint32_t *thr = nullptr;    // thalamic thresholds of every (instance, population),
+                                    // followed by 8 padding entries
+  const uint2 *pmeta = nullptr;     // [n_inst * 8]: (first threshold, count)
+  uint32_t nthr = 0;                // thresholds without the padding
+  uint32_t thr_lds = 0;             // 1: tables fit the kernels' LDS copies
   float *U = nullptr, *I = nullptr;
   uint32_t *R4 = nullptr;           // 4 refractory counters per quad (bytes)
   int32_t *W = nullptr;             // [64][ntot]
@@ -40,10 +58,11 @@ struct DeviceNet {
   uint32_t *spk_list = nullptr;     // [2][ntot]
   uint64_t *raster = nullptr;       // (step << 32) | global id
   uint64_t raster_cap = 0;
-  int64_t *wave_ctr = nullptr;      // [nquads / 64][4]: spikes, thalamic, consumed
+  int64_t *wave_ctr = nullptr;      // [nquads / 64][4]: spikes, thalamic, consumed, events
   uint64_t *events = nullptr;       // [n_inst]
   DevConsts *consts = nullptr;
   Control *ctl = nullptr;
+  SegEntry *seg_list = nullptr;     // persistent: [3][ntot * nwin_max]
 };
 
 struct LaunchShape {
@@ -58,5 +77,12 @@ hipError_t launch_propagators(const DeviceNet &d, hipStream_t s);
 // ctl->t_base + k.  Advances ctl->t_base by n at the end.
 hipError_t launch_stepwise(const DeviceNet &d, const LaunchShape &sh, uint32_t n, hipStream_t s);
 hipError_t launch_reset_raster(const DeviceNet &d, hipStream_t s);
+// Persistent engine: one cooperative launch of sh.grid blocks runs n steps
+// (n grid barriers); the device state is canonical again when it returns.
+hipError_t launch_persistent(const DeviceNet &d, const LaunchShape &sh, uint32_t n, hipStream_t s);
+// Largest co-resident grid of the persistent kernel for a shape, and the
+// quad capacity per thread it was compiled for.
+int persistent_max_grid(const DeviceNet &d, uint32_t block, uint32_t qpt);
+uint32_t persistent_qmax(uint32_t qpt);
 
 }  // namespace snn

@@ -7,6 +7,12 @@
 // compiled with -ffp-contract=off, denormals kept), synaptic input summed as
 // exact int32 in 2^-8 pA, so the order in which atomics land cannot change
 // the result.
+//
+// Latency, not bandwidth, bounds one microcircuit step (a few hundred KB of
+// traffic), so the kernels are built to keep every memory round trip off the
+// dependent chain: thalamic tables sit in LDS and are scanned eight entries at
+// a time, and each thread issues the record loads of all its synapses before
+// any of their atomics.
 #include "engine.hpp"
 
 namespace snn {
@@ -36,11 +42,50 @@ hipError_t launch_propagators(const DeviceNet &d, hipStream_t s) {
 }
 
 // ---------------------------------------------------------------------------
-// Neuron update of one quad (4 consecutive neurons of one instance).
+// Shared pieces of the neuron update.
 // ---------------------------------------------------------------------------
 struct Props {
   float p11, p22, p21;
 };
+
+// Thalamic tables in LDS (or straight from global memory when the batch's
+// tables are too large); copied by the whole block.
+struct ThrTables {
+  uint32_t thr[kThrLds + 8];
+  uint2 meta[kMetaLds];
+};
+
+template <bool LDS>
+__device__ __forceinline__ void stage_tables(const DeviceNet &d, ThrTables &s) {
+  if (!LDS) return;
+  for (uint32_t i = threadIdx.x; i < d.nthr + 8; i += blockDim.x) s.thr[i] = d.thr[i];
+  for (uint32_t i = threadIdx.x; i < d.n_inst * 8; i += blockDim.x) s.meta[i] = d.pmeta[i];
+}
+
+template <bool LDS>
+__device__ __forceinline__ uint2 table_meta(const DeviceNet &d, const ThrTables &s, uint32_t idx) {
+  return LDS ? s.meta[idx] : d.pmeta[idx];
+}
+
+// T = #{k < len : u >= thr[off + k]} for a sorted table.  The first eight
+// entries are read unconditionally (tables are padded by 8), so the loads do
+// not depend on each other; longer counts (P ~ 1e-4 at the model's rates)
+// continue one entry at a time.
+template <bool LDS>
+__device__ __forceinline__ uint32_t thalamic_count(const DeviceNet &d, const ThrTables &s,
+                                                   uint2 m, uint32_t u) {
+  const uint32_t *tab = LDS ? s.thr : d.thr;
+  uint32_t T = 0;
+#pragma unroll
+  for (uint32_t k = 0; k < 8; ++k) {
+    const uint32_t v = tab[m.x + k];
+    T += (k < m.y && u >= v) ? 1u : 0u;
+  }
+  if (T == 8u) {
+    while (T < m.y && u >= tab[m.x + T]) ++T;
+  }
+  return T;
+}
 
 __device__ __forceinline__ uint32_t population(const InstDev *__restrict__ ip, uint32_t local) {
   uint32_t p = 0;
@@ -49,54 +94,66 @@ __device__ __forceinline__ uint32_t population(const InstDev *__restrict__ ip, u
   return p;
 }
 
-// eqn:mem / eqn:ref / eqn:psc for the quad; w holds the ring-buffer row t of
-// the four neurons.  Returns a 4-bit mask of the neurons that spiked.
-__device__ __forceinline__ uint32_t update_quad(const InstDev *__restrict__ ip,
-                                                const uint32_t *__restrict__ thr, uint32_t lq,
-                                                uint64_t t, Props k, float (&u)[4], float (&i)[4],
-                                                uint32_t &r4, const int32_t (&w)[4],
-                                                uint32_t &tsum, int64_t &consumed) {
-  const uint64_t seed = ip->seed;
+// Population code of a quad: 3 bits per neuron, and bit 12 + m set when
+// neuron m is a real neuron of the instance (not padding).
+__device__ __forceinline__ uint32_t quad_code(const InstDev *__restrict__ ip, uint32_t lq) {
+  uint32_t c = 0;
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    const uint32_t local = lq * 4u + uint32_t(m);
+    if (local < ip->n) c |= (population(ip, local) << (3 * m)) | (1u << (12 + m));
+  }
+  return c;
+}
+
+// eqn:mem and eqn:ref for step t, with the thalamic counts T_t of the quad
+// (packed one byte per neuron into tp).  Returns a 4-bit spike mask.
+template <bool LDS>
+__device__ __forceinline__ uint32_t decide_quad(const DeviceNet &d, const ThrTables &s,
+                                                uint32_t inst, uint64_t seed, uint32_t lq,
+                                                uint32_t code, uint64_t t, Props k,
+                                                float (&u)[4], const float (&i)[4], uint32_t &r4,
+                                                uint32_t &tp, uint32_t &tsum) {
   const Philox4 x = philox4x32_10(lq, uint32_t(t), uint32_t(t >> 32), kStreamThalamic,
                                   uint32_t(seed), uint32_t(seed >> 32));
-  const uint32_t n = ip->n;
-  const int32_t wext = ip->w_ext_q;
-  uint32_t flags = 0, rout = 0;
+  uint32_t flags = 0, rout = 0, tpk = 0;
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    uint32_t r = (r4 >> (8 * j)) & 0xFFu;
-    const uint32_t local = lq * 4u + uint32_t(j);
-    if (local < n) {
-      const uint32_t p = population(ip, local);
-      const uint32_t off = ip->thr_off[p];
-      const uint32_t len = ip->thr_len[p];
-      uint32_t T = 0;
-      while (T < len && x.v[j] >= thr[off + T]) ++T;
+  for (int m = 0; m < 4; ++m) {
+    uint32_t r = (r4 >> (8 * m)) & 0xFFu;
+    if ((code >> (12 + m)) & 1u) {
+      const uint2 meta = table_meta<LDS>(d, s, inst * 8u + ((code >> (3 * m)) & 7u));
+      const uint32_t T = thalamic_count<LDS>(d, s, meta, x.v[m]);
+      tpk |= T << (8 * m);
+      tsum += T;
       if (r == 0) {
-        const float a = k.p22 * u[j];
-        const float b = k.p21 * i[j];
+        const float a = k.p22 * u[m];
+        const float b = k.p21 * i[m];
         float xm = a + b;
         if (xm >= kTheta) {
-          flags |= 1u << j;
+          flags |= 1u << m;
           xm = 0.0f;
           r = kRefSteps;
         }
-        u[j] = xm;
+        u[m] = xm;
       } else {
-        u[j] = 0.0f;
+        u[m] = 0.0f;
         r -= 1;
       }
-      const int32_t q = int32_t(T) * wext + w[j];
-      const float c = k.p11 * i[j];
-      const float e = __int2float_rn(q) * 0x1p-8f;
-      i[j] = c + e;
-      tsum += T;
-      consumed += w[j];
     }
-    rout |= r << (8 * j);
+    rout |= r << (8 * m);
   }
   r4 = rout;
+  tp = tpk;
   return flags;
+}
+
+// eqn:psc: I <- p11 I + (T w_ext + W) 2^-8, the input summed as an integer.
+__device__ __forceinline__ float next_current(float i, int32_t T, int32_t wext, int32_t w,
+                                              float p11) {
+  const int32_t q = T * wext + w;
+  const float c = p11 * i;
+  const float e = __int2float_rn(q) * 0x1p-8f;
+  return c + e;
 }
 
 __device__ __forceinline__ uint64_t lanemask_lt() {
@@ -120,21 +177,113 @@ __device__ __forceinline__ void wave_compact(uint32_t flags, uint32_t &lane_off,
 
 __device__ __forceinline__ float4 ld4(const float *p) { return *reinterpret_cast<const float4 *>(p); }
 
+template <int BS>
+__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t *s_tmp,
+                                                         uint32_t &total) {
+  constexpr int NW = BS / 64;
+  const uint32_t lane = __lane_id(), wave = threadIdx.x >> 6;
+  uint32_t x = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t y = __shfl_up(x, o);
+    if (lane >= uint32_t(o)) x += y;
+  }
+  if (lane == 63) s_tmp[wave] = x;
+  __syncthreads();
+  uint32_t before = 0, all = 0;
+#pragma unroll
+  for (int w = 0; w < NW; ++w) {
+    const uint32_t c = s_tmp[w];
+    before += uint32_t(w) < wave ? c : 0u;
+    all += c;
+  }
+  __syncthreads();
+  total = all;
+  return before + x - v;
+}
+
+// ---------------------------------------------------------------------------
+// Push transfer of one batch of staged segments (lst:push2): synapse e of the
+// concatenated segments goes to thread e mod TT.  Each thread first locates
+// and loads up to 8 of its records, then issues their atomics, so one record
+// round trip covers them all.  Delay d lands in row (t_src + d) mod 64.
+// ---------------------------------------------------------------------------
+struct SegStage {
+  uint64_t start;
+  uint32_t len;
+  uint32_t tbase;
+};
+
+template <bool COMP>
+__device__ __forceinline__ void deliver_batch(const DeviceNet &d, uint64_t t_src,
+                                              const SegStage *s_seg, const uint32_t *s_excl,
+                                              uint32_t nb, uint32_t total, uint32_t gt,
+                                              uint32_t TT) {
+  constexpr int U = 8;
+  for (uint32_t e0 = gt; e0 < total; e0 += TT * U) {
+    uint64_t idx[U];
+    uint32_t tb[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const uint32_t e = e0 + uint32_t(u) * TT;
+      idx[u] = ~0ull;
+      tb[u] = 0;
+      if (e < total) {
+        uint32_t lo = 0, hi = nb;
+        while (hi - lo > 1) {
+          const uint32_t mid = (lo + hi) >> 1;
+          if (s_excl[mid] <= e) lo = mid; else hi = mid;
+        }
+        idx[u] = s_seg[lo].start + (e - s_excl[lo]);
+        tb[u] = s_seg[lo].tbase;
+      }
+    }
+    uint32_t tgt[U], dl[U];
+    int32_t wq[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      tgt[u] = 0;
+      dl[u] = 0;
+      wq[u] = 0;
+      if (idx[u] != ~0ull) {
+        if (COMP) {
+          tgt[u] = tb[u] + d.tgt16[idx[u]];
+          wq[u] = int32_t(d.w16[idx[u]]) * 8;
+          dl[u] = d.d8[idx[u]];
+        } else {
+          const uint64_t rec = d.rec8[idx[u]];
+          const uint32_t hiw = uint32_t(rec >> 32);
+          wq[u] = int32_t(uint32_t(rec));
+          tgt[u] = hiw >> 6;
+          dl[u] = hiw & 63u;
+        }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (idx[u] != ~0ull)
+        atomicAdd(d.W + size_t((t_src + dl[u]) & (kRing - 1)) * d.ntot + tgt[u], wq[u]);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Stepwise engine, kernel 1 of 2: update every neuron for step t, read and
 // clear ring row t, append spikes to the step's sender list and the raster.
 // ---------------------------------------------------------------------------
-template <int BS>
+template <int BS, bool LDS>
 __global__ __launch_bounds__(BS) void k_update(DeviceNet d, uint32_t k_step) {
   constexpr int NW = BS / 64;
+  __shared__ ThrTables s_tab;
   __shared__ uint32_t s_wave[NW];
   __shared__ uint32_t s_base;
   __shared__ unsigned long long s_rbase;
+  stage_tables<LDS>(d, s_tab);
   const uint64_t t = d.ctl->t_base + k_step;
   const uint32_t slot = uint32_t(t & 1u);
   const uint32_t q = blockIdx.x * BS + threadIdx.x;
   const uint32_t wave = threadIdx.x >> 6;
   if (blockIdx.x == 0 && threadIdx.x == 0) d.ctl->spk_cnt[slot ^ 1u] = 0;
+  __syncthreads();
 
   uint32_t flags = 0, tsum = 0, gid0 = 0;
   int64_t consumed = 0;
@@ -153,8 +302,17 @@ __global__ __launch_bounds__(BS) void k_update(DeviceNet d, uint32_t k_step) {
     float u[4] = {uv.x, uv.y, uv.z, uv.w};
     float i[4] = {iv.x, iv.y, iv.z, iv.w};
     const int32_t w[4] = {w4.x, w4.y, w4.z, w4.w};
-    uint32_t r4 = d.R4[q];
-    flags = update_quad(ip, d.thr, lq, t, k, u, i, r4, w, tsum, consumed);
+    uint32_t r4 = d.R4[q], tp = 0;
+    const uint32_t code = quad_code(ip, lq);
+    flags = decide_quad<LDS>(d, s_tab, inst, ip->seed, lq, code, t, k, u, i, r4, tp, tsum);
+    const int32_t wext = ip->w_ext_q;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      if ((code >> (12 + m)) & 1u) {
+        i[m] = next_current(i[m], int32_t((tp >> (8 * m)) & 0xFFu), wext, w[m], k.p11);
+        consumed += w[m];
+      }
+    }
     *reinterpret_cast<float4 *>(d.U + 4 * size_t(q)) = make_float4(u[0], u[1], u[2], u[3]);
     *reinterpret_cast<float4 *>(d.I + 4 * size_t(q)) = make_float4(i[0], i[1], i[2], i[3]);
     d.R4[q] = r4;
@@ -212,45 +370,18 @@ __global__ __launch_bounds__(BS) void k_update(DeviceNet d, uint32_t k_step) {
 }
 
 // ---------------------------------------------------------------------------
-// Stepwise engine, kernel 2 of 2: push transfer (lst:push2).  The senders of
-// step t and their storage segments are staged in LDS with an exclusive
-// prefix over segment lengths; the whole grid then strides over the
-// concatenated synapse range, one synapse per thread per iteration, and adds
-// each weight to W[(t + d) mod 64][target] with a device-scope int32 atomic.
+// Stepwise engine, kernel 2 of 2: push transfer of the senders of step t.
+// Every block stages the senders' storage segments in LDS with an exclusive
+// prefix over their lengths, then the whole grid shares the concatenated
+// synapse range (deliver_batch).
 // ---------------------------------------------------------------------------
 constexpr int kSegCap = 1024;
-
-template <int BS>
-__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t *s_tmp,
-                                                         uint32_t &total) {
-  constexpr int NW = BS / 64;
-  const uint32_t lane = __lane_id(), wave = threadIdx.x >> 6;
-  uint32_t x = v;
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const uint32_t y = __shfl_up(x, o);
-    if (lane >= uint32_t(o)) x += y;
-  }
-  if (lane == 63) s_tmp[wave] = x;
-  __syncthreads();
-  uint32_t before = 0, all = 0;
-#pragma unroll
-  for (int w = 0; w < NW; ++w) {
-    const uint32_t c = s_tmp[w];
-    before += uint32_t(w) < wave ? c : 0u;
-    all += c;
-  }
-  __syncthreads();
-  total = all;
-  return before + x - v;
-}
 
 template <int BS, bool COMP>
 __global__ __launch_bounds__(BS) void k_transfer(DeviceNet d, uint32_t k_step) {
   constexpr int IPT = kSegCap / BS;
-  __shared__ uint64_t s_start[kSegCap];
+  __shared__ SegStage s_seg[kSegCap];
   __shared__ uint32_t s_excl[kSegCap];
-  __shared__ uint32_t s_tbase[kSegCap];
   __shared__ uint32_t s_tmp[BS / 64];
   const uint64_t t = d.ctl->t_base + k_step;
   const uint32_t slot = uint32_t(t & 1u);
@@ -263,7 +394,6 @@ __global__ __launch_bounds__(BS) void k_transfer(DeviceNet d, uint32_t k_step) {
   for (uint32_t b0 = 0; b0 < n; b0 += per_batch) {
     const uint32_t nb = min(per_batch, n - b0);
     const uint32_t nseg = nb * nwin;
-    // Stage this thread's IPT consecutive segments.
     uint32_t len[IPT];
     uint32_t mysum = 0;
 #pragma unroll
@@ -288,8 +418,9 @@ __global__ __launch_bounds__(BS) void k_transfer(DeviceNet d, uint32_t k_step) {
                       (unsigned long long)row);
           }
         }
-        s_start[s] = st;
-        s_tbase[s] = ip->gbase + (win << kTargetBlockBits);
+        s_seg[s].start = st;
+        s_seg[s].len = len[m];
+        s_seg[s].tbase = ip->gbase + (win << kTargetBlockBits);
       }
       mysum += len[m];
     }
@@ -302,30 +433,8 @@ __global__ __launch_bounds__(BS) void k_transfer(DeviceNet d, uint32_t k_step) {
       run += len[m];
     }
     __syncthreads();
-
-    for (uint32_t e = blockIdx.x * BS + threadIdx.x; e < total; e += gridDim.x * BS) {
-      // last segment whose exclusive prefix is <= e (empty segments skipped)
-      uint32_t lo = 0, hi = nseg;
-      while (hi - lo > 1) {
-        const uint32_t mid = (lo + hi) >> 1;
-        if (s_excl[mid] <= e) lo = mid; else hi = mid;
-      }
-      const uint64_t idx = s_start[lo] + (e - s_excl[lo]);
-      uint32_t tgt, dl;
-      int32_t wq;
-      if (COMP) {
-        tgt = s_tbase[lo] + d.tgt16[idx];
-        wq = int32_t(d.w16[idx]) * 8;
-        dl = d.d8[idx];
-      } else {
-        const uint64_t rec = d.rec8[idx];
-        const uint32_t hiw = uint32_t(rec >> 32);
-        wq = int32_t(uint32_t(rec));
-        tgt = hiw >> 6;
-        dl = hiw & 63u;
-      }
-      atomicAdd(d.W + size_t((t + dl) & (kRing - 1)) * d.ntot + tgt, wq);
-    }
+    deliver_batch<COMP>(d, t, s_seg, s_excl, nseg, total, blockIdx.x * BS + threadIdx.x,
+                        gridDim.x * BS);
     __syncthreads();
   }
 }
@@ -350,7 +459,10 @@ hipError_t launch_stepwise(const DeviceNet &d, const LaunchShape &sh, uint32_t n
   constexpr int BS = 256;
   const uint32_t ublocks = (d.nquads + BS - 1) / BS;
   for (uint32_t k = 0; k < n; ++k) {
-    hipLaunchKernelGGL(k_update<BS>, dim3(ublocks), dim3(BS), 0, s, d, k);
+    if (d.thr_lds)
+      hipLaunchKernelGGL((k_update<BS, true>), dim3(ublocks), dim3(BS), 0, s, d, k);
+    else
+      hipLaunchKernelGGL((k_update<BS, false>), dim3(ublocks), dim3(BS), 0, s, d, k);
     if (d.syn_format == SNN_SYN_COMPRESSED5)
       hipLaunchKernelGGL((k_transfer<BS, true>), dim3(sh.scatter_blocks), dim3(BS), 0, s, d, k);
     else
@@ -358,6 +470,380 @@ hipError_t launch_stepwise(const DeviceNet &d, const LaunchShape &sh, uint32_t n
   }
   hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, s, d.ctl, n);
   return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Persistent engine: one cooperative launch runs a chunk of steps with one
+// grid-wide barrier per step.
+//
+// Iteration `it` (step t = t0 + it) of every block:
+//   (a) completes step t-1 for the block's neurons: reads and clears ring row
+//       t-1 with device-coherent loads and stores, I_t = p11 I + (T w + W) 2^-8;
+//   (b) decides step t (eqn:mem / eqn:ref) and publishes the storage
+//       segments of its senders to the rotating segment list of step t;
+//   (c) delivers the senders of step t-1 (published in the previous
+//       iteration) into rows t .. t+62 -- never row t-1, which (a) reads.
+// Row t-1 is complete when (a) reads it: its last contributions come from the
+// senders of step t-2 with delay 1, delivered in iteration it-1 before the
+// barrier.  After the last step one more (a)+(c) pass leaves the state
+// canonical (all senders delivered, I of the next step computed).
+//
+// Everything one block writes and another reads after a barrier goes through
+// device-scope atomics (ring adds, list counts) or device-scope atomic loads
+// and stores (ring reads and clears, list entries), so the barrier needs no cache
+// write-back or invalidation: each wave waits until its own memory operations
+// are performed (vmcnt 0), then one thread per block arrives and polls.  Every
+// wait is bounded; on expiry the kernel records an error and all blocks leave.
+// ---------------------------------------------------------------------------
+constexpr uint32_t kSpec = 64;   // list entries fetched together with the count
+
+__device__ __forceinline__ uint32_t ld_ag(const uint32_t *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint64_t ld_ag(const uint64_t *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_ag(uint32_t *p, uint32_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_ag(uint64_t *p, uint64_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ SegStage ld_entry(const SegEntry *e) {
+  SegStage r;
+  r.start = ld_ag(&e->start);
+  const uint64_t lt = ld_ag(reinterpret_cast<const uint64_t *>(&e->len));
+  r.len = uint32_t(lt);
+  r.tbase = uint32_t(lt >> 32);
+  return r;
+}
+__device__ __forceinline__ void st_entry(SegEntry *e, uint64_t start, uint32_t len, uint32_t tbase) {
+  st_ag(&e->start, start);
+  st_ag(reinterpret_cast<uint64_t *>(&e->len), uint64_t(len) | (uint64_t(tbase) << 32));
+}
+
+__device__ __forceinline__ bool grid_barrier(Control *ctl, uint64_t target, uint32_t spin_limit,
+                                             uint32_t *s_flag) {
+  __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): this wave's stores and atomics are performed
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __hip_atomic_fetch_add(&ctl->barrier, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    uint32_t ok = 1, spins = 0;
+    while (ld_ag(&ctl->barrier) < target) {
+      __builtin_amdgcn_s_sleep(1);
+      if ((++spins & 255u) == 0 && (ld_ag(&ctl->error) != 0 || spins > spin_limit)) {
+        st_ag(&ctl->error, 1u);
+        ok = 0;
+        break;
+      }
+    }
+    *s_flag = ok;
+  }
+  __syncthreads();
+  return *s_flag != 0;
+}
+
+template <int BS, int QMAX, bool COMP, bool LDS>
+__global__ __launch_bounds__(BS) void k_persistent(DeviceNet d, uint32_t n_steps, uint32_t qpt,
+                                                    uint32_t spin_limit) {
+  constexpr int NW = BS / 64;
+  constexpr int IPT = kSegCap / BS;
+  __shared__ ThrTables s_tab;
+  __shared__ SegStage s_seg[kSegCap];
+  __shared__ uint32_t s_excl[kSegCap];
+  __shared__ uint32_t s_tmp[NW];
+  __shared__ uint32_t s_wave[NW];
+  __shared__ uint32_t s_base, s_flag, s_n;
+  __shared__ unsigned long long s_rbase;
+
+  const uint32_t G = gridDim.x;
+  const uint32_t TT = G * BS;
+  const uint32_t gt = blockIdx.x * BS + threadIdx.x;
+  const uint32_t wave = threadIdx.x >> 6;
+  const uint32_t lane = __lane_id();
+  const uint64_t t0 = d.ctl->t_base;
+  const Props k{d.consts->p11, d.consts->p22, d.consts->p21};
+  const uint32_t nwin = d.nwin_max;
+  const size_t lstride = size_t(d.ntot) * nwin;
+  stage_tables<LDS>(d, s_tab);
+
+  // Owned quads q = gt + j * TT: state, thalamic counts of the last decided
+  // step, quad info and population code stay in registers for the chunk.
+  float U[QMAX][4], I[QMAX][4];
+  uint32_t R[QMAX], Tp[QMAX], QI[QMAX], PC[QMAX], c_spk[QMAX], c_poi[QMAX];
+  int64_t c_con[QMAX];
+  uint64_t c_ev[QMAX];
+#pragma unroll
+  for (int j = 0; j < QMAX; ++j) {
+    const uint32_t q = gt + uint32_t(j) * TT;
+    c_spk[j] = c_poi[j] = 0;
+    c_con[j] = 0;
+    c_ev[j] = 0;
+    Tp[j] = R[j] = QI[j] = PC[j] = 0;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) U[j][m] = I[j][m] = 0.0f;
+    if (uint32_t(j) < qpt && q < d.nquads) {
+      const float4 uv = ld4(d.U + 4 * size_t(q));
+      const float4 iv = ld4(d.I + 4 * size_t(q));
+      U[j][0] = uv.x; U[j][1] = uv.y; U[j][2] = uv.z; U[j][3] = uv.w;
+      I[j][0] = iv.x; I[j][1] = iv.y; I[j][2] = iv.z; I[j][3] = iv.w;
+      R[j] = d.R4[q];
+      QI[j] = d.qinfo[q];
+      const InstDev *ip = d.inst + __builtin_amdgcn_readfirstlane(QI[j] >> 24);
+      PC[j] = quad_code(ip, QI[j] & 0xFFFFFFu);
+    }
+  }
+  __syncthreads();
+
+  for (uint32_t it = 0; it <= n_steps; ++it) {
+    const uint64_t t = t0 + it;
+    const bool has_prev = it > 0;
+    const bool decide = it < n_steps;
+    SegEntry *lcur = d.seg_list + size_t(it % 3) * lstride;
+    const SegEntry *lprev = d.seg_list + size_t((it + 2) % 3) * lstride;
+
+    // (c) part 1: the count of step t-1's segments and the first kSpec of them.
+    uint32_t nprev = 0;
+    SegStage spec{0, 0, 0};
+    if (has_prev && wave == 0) {
+      nprev = ld_ag(&d.ctl->lcnt[(it + 2) % 3]);
+      spec = ld_entry(lprev + lane);
+    }
+    if (decide && gt == 0) st_ag(&d.ctl->lcnt[(it + 1) % 3], 0u);
+
+    // (a) complete step t-1.  Ring words are read and cleared with
+    // device-coherent 8-byte loads and stores (two per quad): no atomic unit
+    // is involved, and the row has no other writer in this iteration.
+    if (has_prev) {
+      int32_t *wrow = d.W + size_t((t - 1) & (kRing - 1)) * d.ntot;
+#pragma unroll
+      for (int j = 0; j < QMAX; ++j) {
+        const uint32_t q = gt + uint32_t(j) * TT;
+        if (uint32_t(j) < qpt && q < d.nquads) {
+          const InstDev *ip = d.inst + __builtin_amdgcn_readfirstlane(QI[j] >> 24);
+          const int32_t wext = ip->w_ext_q;
+          uint64_t *wp = reinterpret_cast<uint64_t *>(wrow + 4 * size_t(q));
+          const uint64_t w01 = ld_ag(wp), w23 = ld_ag(wp + 1);
+          st_ag(wp, 0ull);
+          st_ag(wp + 1, 0ull);
+          const int32_t w[4] = {int32_t(uint32_t(w01)), int32_t(uint32_t(w01 >> 32)),
+                                int32_t(uint32_t(w23)), int32_t(uint32_t(w23 >> 32))};
+#pragma unroll
+          for (int m = 0; m < 4; ++m) {
+            if ((PC[j] >> (12 + m)) & 1u) {
+              I[j][m] = next_current(I[j][m], int32_t((Tp[j] >> (8 * m)) & 0xFFu), wext, w[m], k.p11);
+              c_con[j] += w[m];
+            }
+          }
+        }
+      }
+    }
+
+    // (b) decide step t and publish the senders' segments.
+    if (decide) {
+      uint32_t flags[QMAX];
+      uint32_t lane_base[QMAX];
+      uint32_t wtot = 0;
+#pragma unroll
+      for (int j = 0; j < QMAX; ++j) {
+        flags[j] = 0;
+        const uint32_t q = gt + uint32_t(j) * TT;
+        if (uint32_t(j) < qpt && q < d.nquads) {
+          const uint32_t inst = __builtin_amdgcn_readfirstlane(QI[j] >> 24);
+          const InstDev *ip = d.inst + inst;
+          flags[j] = decide_quad<LDS>(d, s_tab, inst, ip->seed, QI[j] & 0xFFFFFFu, PC[j], t, k,
+                                      U[j], I[j], R[j], Tp[j], c_poi[j]);
+        }
+        uint32_t lo, tot;
+        wave_compact(flags[j], lo, tot);
+        lane_base[j] = wtot + lo;
+        wtot += tot;
+      }
+      if (lane == 0) s_wave[wave] = wtot;
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        uint32_t run = 0;
+        for (int w = 0; w < NW; ++w) {
+          const uint32_t c = s_wave[w];
+          s_wave[w] = run;
+          run += c;
+        }
+        if (run) {
+          s_base = atomicAdd(&d.ctl->lcnt[it % 3], run * nwin);
+          s_rbase = atomicAdd(reinterpret_cast<unsigned long long *>(&d.ctl->raster_n),
+                              (unsigned long long)run);
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int j = 0; j < QMAX; ++j) {
+        if (!flags[j]) continue;
+        const uint32_t q = gt + uint32_t(j) * TT;
+        const InstDev *ip = d.inst + (QI[j] >> 24);
+        const uint32_t lq = QI[j] & 0xFFFFFFu;
+        const uint32_t inw = ip->nwin;
+        uint32_t o = s_wave[wave] + lane_base[j];
+        c_spk[j] += __popc(flags[j]);
+        for (int m = 0; m < 4; ++m) {
+          if (!((flags[j] >> m) & 1u)) continue;
+          const uint32_t gid = 4 * q + uint32_t(m);
+          const uint64_t sg = uint64_t(ip->seg_base) + uint64_t(lq * 4u + uint32_t(m)) * inw;
+          const uint64_t row0 = d.seg_ptr[sg];
+          c_ev[j] += d.seg_ptr[sg + inw] - row0;
+          SegEntry *dst = lcur + size_t(s_base) + size_t(o) * nwin;
+          for (uint32_t w = 0; w < nwin; ++w) {
+            uint64_t st = 0;
+            uint32_t len = 0;
+            if (w < inw) {
+              st = d.seg_ptr[sg + w];
+              len = uint32_t(d.seg_ptr[sg + w + 1] - st);
+            }
+            st_entry(dst + w, st, len, COMP ? ip->gbase + (w << kTargetBlockBits) : 0u);
+          }
+          const uint64_t pos = s_rbase + o;
+          if (pos < d.raster_cap)
+            d.raster[pos] = (t << 32) | gid;
+          else
+            d.ctl->overflow = 1;
+          ++o;
+        }
+      }
+    }
+
+    // (c) part 2: deliver the senders of step t-1 into rows t .. t+62.
+    if (has_prev) {
+      if (wave == 0 && lane == 0) s_n = nprev;
+      __syncthreads();
+      const uint32_t n = s_n;
+      for (uint32_t b0 = 0; b0 < n; b0 += kSegCap) {
+        const uint32_t nb = min(uint32_t(kSegCap), n - b0);
+        if (b0 == 0) {
+          if (wave == 0 && lane < nb) s_seg[lane] = spec;
+          for (uint32_t s2 = kSpec + threadIdx.x; s2 < nb; s2 += BS) s_seg[s2] = ld_entry(lprev + s2);
+        } else {
+          for (uint32_t s2 = threadIdx.x; s2 < nb; s2 += BS) s_seg[s2] = ld_entry(lprev + b0 + s2);
+        }
+        __syncthreads();
+        uint32_t len[IPT];
+        uint32_t mysum = 0;
+#pragma unroll
+        for (int m = 0; m < IPT; ++m) {
+          const uint32_t s2 = threadIdx.x * IPT + m;
+          len[m] = s2 < nb ? s_seg[s2].len : 0u;
+          mysum += len[m];
+        }
+        uint32_t total;
+        uint32_t run = block_exclusive_scan<BS>(mysum, s_tmp, total);
+#pragma unroll
+        for (int m = 0; m < IPT; ++m) {
+          const uint32_t s2 = threadIdx.x * IPT + m;
+          if (s2 < nb) s_excl[s2] = run;
+          run += len[m];
+        }
+        __syncthreads();
+        deliver_batch<COMP>(d, t - 1, s_seg, s_excl, nb, total, gt, TT);
+        __syncthreads();
+      }
+    }
+
+    if (it == n_steps) break;
+    if (!grid_barrier(d.ctl, uint64_t(it + 1) * G, spin_limit, &s_flag)) break;
+  }
+
+  // State back to memory; counters to the per-wave slots.
+#pragma unroll
+  for (int j = 0; j < QMAX; ++j) {
+    const uint32_t q = gt + uint32_t(j) * TT;
+    const bool act = uint32_t(j) < qpt && q < d.nquads;
+    if (act) {
+      *reinterpret_cast<float4 *>(d.U + 4 * size_t(q)) = make_float4(U[j][0], U[j][1], U[j][2], U[j][3]);
+      *reinterpret_cast<float4 *>(d.I + 4 * size_t(q)) = make_float4(I[j][0], I[j][1], I[j][2], I[j][3]);
+      d.R4[q] = R[j];
+    }
+    uint64_t sp = c_spk[j], po = c_poi[j], ev = c_ev[j];
+    int64_t co = c_con[j];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      sp += __shfl_xor(sp, o);
+      po += __shfl_xor(po, o);
+      ev += __shfl_xor(ev, o);
+      co += __shfl_xor(co, o);
+    }
+    if (lane == 0 && uint32_t(j) < qpt && (q >> 6) < (d.nquads >> 6)) {
+      int64_t *c = d.wave_ctr + 4 * size_t(q >> 6);
+      c[0] += int64_t(sp);
+      c[1] += int64_t(po);
+      c[2] += co;
+      c[3] += int64_t(ev);
+    }
+  }
+  // The last block to finish resets the shared control words for the next
+  // launch and advances the step counter.
+  __builtin_amdgcn_s_waitcnt(0x0F70);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const uint64_t done =
+        __hip_atomic_fetch_add(&d.ctl->exit_count, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (done == G - 1) {
+      st_ag(&d.ctl->lcnt[0], 0u);
+      st_ag(&d.ctl->lcnt[1], 0u);
+      st_ag(&d.ctl->lcnt[2], 0u);
+      st_ag(&d.ctl->barrier, 0ull);
+      st_ag(&d.ctl->exit_count, 0ull);
+      st_ag(&d.ctl->t_base, t0 + n_steps);
+    }
+  }
+}
+
+using PersistentFn = void (*)(DeviceNet, uint32_t, uint32_t, uint32_t);
+
+template <bool COMP, bool LDS>
+static PersistentFn pick_persistent(uint32_t block, uint32_t qmax) {
+#define SNN_PK(BSV, QV) \
+  if (block == BSV && qmax == QV) return k_persistent<BSV, QV, COMP, LDS>;
+  SNN_PK(256, 1) SNN_PK(256, 2) SNN_PK(256, 4) SNN_PK(256, 8)
+  SNN_PK(128, 1) SNN_PK(128, 2) SNN_PK(128, 4)
+  SNN_PK(512, 1) SNN_PK(512, 2)
+  SNN_PK(1024, 1)
+#undef SNN_PK
+  return nullptr;
+}
+
+uint32_t persistent_qmax(uint32_t qpt) {
+  return qpt <= 1 ? 1 : qpt <= 2 ? 2 : qpt <= 4 ? 4 : qpt <= 8 ? 8 : 0;
+}
+
+static PersistentFn persistent_fn(const DeviceNet &d, uint32_t block, uint32_t qpt) {
+  const uint32_t qmax = persistent_qmax(qpt);
+  if (!qmax) return nullptr;
+  const bool comp = d.syn_format == SNN_SYN_COMPRESSED5;
+  if (d.thr_lds)
+    return comp ? pick_persistent<true, true>(block, qmax) : pick_persistent<false, true>(block, qmax);
+  return comp ? pick_persistent<true, false>(block, qmax) : pick_persistent<false, false>(block, qmax);
+}
+
+int persistent_max_grid(const DeviceNet &d, uint32_t block, uint32_t qpt) {
+  PersistentFn fn = persistent_fn(d, block, qpt);
+  if (!fn) return 0;
+  int per_cu = 0, dev = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(fn),
+                                                   int(block), 0) != hipSuccess)
+    return 0;
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return 0;
+  return per_cu * prop.multiProcessorCount;
+}
+
+hipError_t launch_persistent(const DeviceNet &d, const LaunchShape &sh, uint32_t n, hipStream_t s) {
+  PersistentFn fn = persistent_fn(d, sh.block, sh.qpt);
+  if (!fn || sh.grid == 0) return hipErrorInvalidConfiguration;
+  DeviceNet dv = d;
+  uint32_t steps = n, qpt = sh.qpt;
+  // A bounded wait expires after about 2^24 polls (well over 0.1 s).
+  uint32_t spin = 1u << 24;
+  void *args[] = {&dv, &steps, &qpt, &spin};
+  return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(fn), dim3(sh.grid),
+                                    dim3(sh.block), args, 0, s);
 }
 
 }  // namespace snn

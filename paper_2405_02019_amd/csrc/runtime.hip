@@ -137,7 +137,35 @@ uint64_t spike_bound(const snn_net *h, uint64_t steps) {
   return h->n_real * ((steps + kRefSteps) / (kRefSteps + 1));
 }
 
+// Persistent grid: 4 neurons per quad, `qpt` quads per thread, at most the
+// co-resident block count of the kernel.  Fewer blocks make the per-step grid
+// barrier cheaper; more threads give the transfer phase more parallelism.
+int choose_persistent_shape(snn_net *h, uint32_t block, uint32_t grid) {
+  const DeviceNet &d = h->d;
+  const uint32_t blocks[] = {256, 128, 512, 1024};
+  for (uint32_t b : blocks) {
+    if (block && b != block) continue;
+    for (uint32_t q : {1u, 2u, 4u, 8u}) {
+      const int maxg = persistent_max_grid(d, b, q);
+      if (maxg <= 0) continue;
+      uint32_t g = grid ? grid : (d.nquads + b * q - 1) / (b * q);
+      if (g == 0 || g > uint32_t(maxg)) continue;
+      const uint32_t need = (d.nquads + g * b - 1) / (g * b);
+      if (need > q) continue;
+      h->shape.block = b;
+      h->shape.grid = g;
+      h->shape.qpt = need ? need : 1;
+      return SNN_OK;
+    }
+  }
+  return fail(h, SNN_E_RANGE, "no co-resident persistent grid fits %u neurons", d.ntot);
+}
+
 int queue_steps(snn_net *h, uint32_t n) {
+  if (h->engine == SNN_ENGINE_PERSISTENT) {
+    HIP_OK(h, launch_persistent(h->d, h->shape, n, h->stream));
+    return SNN_OK;
+  }
   if (h->graph_exec && n == h->chunk) {
     HIP_OK(h, hipGraphLaunch(h->graph_exec, h->stream));
     return SNN_OK;
@@ -265,6 +293,7 @@ int snn_build(const snn_config *cfg, snn_net **out) {
   // ---- device memory ----
   InstDev *d_inst;
   uint32_t *d_qinfo, *d_thr;
+  uint2 *d_pmeta;
   uint64_t *d_seg, *d_rec8 = nullptr;
   uint16_t *d_tgt16 = nullptr;
   int16_t *d_w16 = nullptr;
@@ -282,7 +311,8 @@ int snn_build(const snn_config *cfg, snn_net **out) {
   } while (0)
   ALLOC(d_inst, ni);
   ALLOC(d_qinfo, d.nquads);
-  ALLOC(d_thr, std::max<uint64_t>(1, nthr));
+  ALLOC(d_thr, nthr + 8);
+  ALLOC(d_pmeta, size_t(ni) * 8);
   ALLOC(d.U, d.ntot);
   ALLOC(d.I, d.ntot);
   ALLOC(d.R4, d.nquads);
@@ -301,12 +331,15 @@ int snn_build(const snn_config *cfg, snn_net **out) {
   ALLOC(d.events, ni);
   ALLOC(d.consts, 1);
   ALLOC(d.ctl, 1);
+  const bool want_persistent = cfg->engine != SNN_ENGINE_STEPWISE;
+  if (want_persistent) ALLOC(d.seg_list, 3 * size_t(d.ntot) * nwin_max);
 #undef ALLOC
 
   // ---- host staging and upload ----
   std::vector<InstDev> hinst(ni);
   std::vector<uint32_t> qinfo(d.nquads, 0);
   std::vector<uint32_t> thr;
+  std::vector<uint2> pmeta(size_t(ni) * 8);
   std::vector<float> u0(d.ntot, 0.0f);
   std::vector<uint64_t> seg;
   seg.reserve(nseg_tot + 1);
@@ -325,6 +358,7 @@ int snn_build(const snn_config *cfg, snn_net **out) {
     for (int p = 0; p < 8; ++p) {
       v.thr_off[p] = uint32_t(thr.size());
       v.thr_len[p] = x.thr_len[p];
+      pmeta[size_t(k) * 8 + p] = make_uint2(v.thr_off[p], v.thr_len[p]);
       thr.insert(thr.end(), x.thr[p], x.thr[p] + x.thr_len[p]);
     }
     v.seg_base = uint32_t(seg.size());
@@ -335,20 +369,25 @@ int snn_build(const snn_config *cfg, snn_net **out) {
     syn_base += x.nsyn;
   }
   seg.push_back(syn_base);
+  thr.resize(thr.size() + 8, 0xFFFFFFFFu);  // padding read by the 8-wide table scan
   if (seg.size() >= (uint64_t(1) << 32)) {
     fail(h, SNN_E_RANGE, "too many storage segments");
     return bail(SNN_E_RANGE);
   }
 #define UPLOAD(dst, src, bytes)                                                     \
   do {                                                                              \
-    if ((bytes) && hipMemcpy((dst), (src), (bytes), hipMemcpyHostToDevice) != hipSuccess) { \
-      fail(h, SNN_E_HIP, "upload of %s failed", #src);                              \
-      return bail(SNN_E_HIP);                                                       \
+    if (bytes) {                                                                    \
+      const hipError_t ue = hipMemcpy((dst), (src), (bytes), hipMemcpyHostToDevice); \
+      if (ue != hipSuccess) {                                                       \
+        fail(h, SNN_E_HIP, "upload of %s failed: %s", #src, hipGetErrorString(ue)); \
+        return bail(SNN_E_HIP);                                                     \
+      }                                                                             \
     }                                                                               \
   } while (0)
   UPLOAD(d_inst, hinst.data(), ni * sizeof(InstDev));
   UPLOAD(d_qinfo, qinfo.data(), qinfo.size() * sizeof(uint32_t));
   UPLOAD(d_thr, thr.data(), thr.size() * sizeof(uint32_t));
+  UPLOAD(d_pmeta, pmeta.data(), pmeta.size() * sizeof(uint2));
   UPLOAD(d.U, u0.data(), u0.size() * sizeof(float));
   UPLOAD(d_seg, seg.data(), seg.size() * sizeof(uint64_t));
   syn_base = 0;
@@ -372,6 +411,9 @@ int snn_build(const snn_config *cfg, snn_net **out) {
   d.inst = d_inst;
   d.qinfo = d_qinfo;
   d.thr = d_thr;
+  d.pmeta = d_pmeta;
+  d.nthr = uint32_t(nthr);
+  d.thr_lds = (nthr <= kThrLds && size_t(ni) * 8 <= kMetaLds) ? 1u : 0u;
   d.seg_ptr = d_seg;
   d.rec8 = d_rec8;
   d.tgt16 = d_tgt16;
@@ -394,10 +436,25 @@ int snn_build(const snn_config *cfg, snn_net **out) {
   }
 
   // ---- engine ----
-  h->engine = SNN_ENGINE_STEPWISE;
   h->shape.block = 256;
-  h->shape.scatter_blocks = cfg->grid_blocks ? cfg->grid_blocks : 1024;
-  if (cfg->use_graphs) {
+  h->shape.scatter_blocks = 1024;
+  h->engine = SNN_ENGINE_STEPWISE;
+  if (want_persistent) {
+    int rc2 = choose_persistent_shape(h, cfg->block_size, cfg->grid_blocks);
+    if (rc2 == SNN_OK) {
+      h->engine = SNN_ENGINE_PERSISTENT;
+    } else if (cfg->engine == SNN_ENGINE_PERSISTENT) {
+      return bail(rc2);
+    }
+  }
+  if (h->engine == SNN_ENGINE_STEPWISE) {
+    if (cfg->block_size && cfg->block_size != 256) {
+      fail(h, SNN_E_INVAL, "the stepwise engine runs 256-thread blocks");
+      return bail(SNN_E_INVAL);
+    }
+    if (cfg->grid_blocks) h->shape.scatter_blocks = cfg->grid_blocks;
+  }
+  if (cfg->use_graphs && h->engine == SNN_ENGINE_STEPWISE) {
     if (hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
       fail(h, SNN_E_HIP, "stream capture failed to start");
       return bail(SNN_E_HIP);
@@ -489,14 +546,16 @@ int snn_read_state(snn_net *h, uint32_t inst, snn_state *out) {
   std::vector<int64_t> wc(4 * size_t(m.npad / 256));
   HIP_OK(h, hipMemcpy(wc.data(), d.wave_ctr + 4 * size_t(m.gbase / 256), wc.size() * sizeof(int64_t),
                       hipMemcpyDeviceToHost));
-  int64_t sp = 0, po = 0, co = 0;
+  int64_t sp = 0, po = 0, co = 0, ev_slots = 0;
   for (size_t w = 0; w < wc.size() / 4; ++w) {
     sp += wc[4 * w];
     po += wc[4 * w + 1];
     co += wc[4 * w + 2];
+    ev_slots += wc[4 * w + 3];
   }
   uint64_t ev = 0;
   HIP_OK(h, hipMemcpy(&ev, d.events + inst, sizeof ev, hipMemcpyDeviceToHost));
+  ev += uint64_t(ev_slots);
   DevConsts kc{};
   HIP_OK(h, hipMemcpy(&kc, d.consts, sizeof kc, hipMemcpyDeviceToHost));
   out->t = h->t;

@@ -103,6 +103,9 @@ def lib():
     """Load libsnn.so; raises if it has not been built."""
     global _lib
     if _lib is None:
+        # torch ships its own HIP runtime; loading it first makes the library
+        # bind to that same runtime instead of a second copy.
+        import torch  # noqa: F401
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
                                "(or python paper_2405_02019_amd/build_lib.py)")

@@ -71,7 +71,7 @@ def test_propagators_on_gpu(P, oracle):
     assert st["w_ext_q"] == k["w_ext_q"] and st["w_f"] == k["w_f"]
 
 
-@pytest.mark.parametrize("engine", ["stepwise"])
+@pytest.mark.parametrize("engine", ["stepwise", "persistent"])
 @pytest.mark.parametrize("fmt,wmode", [("plain", 0), ("compressed", 1)])
 def test_tiny_circuit_bit_exact(P, oracle, engine, fmt, wmode):
     """1 % circuit (772 neurons), 0.1 s of biological time in ragged pieces
@@ -97,6 +97,24 @@ def test_tiny_without_graphs_and_odd_chunks(P, oracle):
             assert_parity(sim, 0, net, osim)
 
 
+@pytest.mark.parametrize("scale,block,grid,chunk", [(0.05, 256, 1, 100), (0.05, 128, 2, 7),
+                                                    (0.05, 512, 1, 1), (0.05, 1024, 1, 33),
+                                                    (0.05, 256, 3, 64), (0.08, 256, 1, 50)])
+def test_persistent_shapes(P, oracle, scale, block, grid, chunk):
+    """Persistent engine with forced shapes: grids of 1-3 blocks, so every
+    thread owns up to 7 quads and every block many senders, and chunks of 1
+    to 100 steps (one grid barrier per step)."""
+    inst = P.Instance(scale=scale, seed=21)
+    say("persistent shape", block, grid, chunk)
+    with P.Simulator(inst, engine="persistent", block_size=block, grid_blocks=grid,
+                     chunk_steps=chunk) as sim:
+        info = sim.info()
+        assert info["engine"] == P.ENGINE_PERSISTENT and info["grid_blocks"] == grid
+        sim.step(211)
+        net, osim = run_oracle(oracle, inst, 0, 211)
+        assert_parity(sim, 0, net, osim)
+
+
 def test_degenerate_drives(P, oracle):
     """No synapses and no thalamic input; then a constant count of one
     thalamic spike per step at a sub-threshold amplitude; then no drive at
@@ -105,8 +123,9 @@ def test_degenerate_drives(P, oracle):
              P.Instance(scale=0.01, seed=3, bg_const_T=1, psp_ext_mv=0.07),
              P.Instance(scale=0.01, seed=4, bg_rate_hz=0.0)]
     for inst in cases:
-        say("degenerate", inst)
-        with P.Simulator(inst) as sim:
+      for engine in ["stepwise", "persistent"]:
+        say("degenerate", engine, inst)
+        with P.Simulator(inst, engine=engine) as sim:
             sim.step(250)
             net, osim = run_oracle(oracle, inst, 0, 250)
             assert_parity(sim, 0, net, osim)
@@ -120,23 +139,35 @@ def test_batched_instances_each_bit_exact(P, oracle):
              P.Instance(scale=0.013, seed=13, g=-3.5, bg_rate_hz=6.5, indegree_mode=1),
              P.Instance(scale=0.002, seed=14)]
     for fmt, wmode in [("plain", 0), ("compressed", 1)]:
-        say("batch", fmt)
-        with P.Simulator(insts, syn_format=fmt) as sim:
+      for engine in ["stepwise", "persistent"]:
+        say("batch", fmt, engine)
+        with P.Simulator(insts, syn_format=fmt, engine=engine) as sim:
             sim.step(400)
             for k, inst in enumerate(insts):
                 net, osim = run_oracle(oracle, inst, wmode, 400)
                 assert_parity(sim, k, net, osim)
 
 
-def test_full_scale_window_bit_exact(P, oracle):
+@pytest.fixture(scope="module")
+def full_oracle(oracle):
+    """Oracle run of the full-scale microcircuit, 300 steps."""
+    say("full scale: building oracle network")
+    return run_oracle(oracle, oracle_stub_instance(), 0, 300)
+
+
+def oracle_stub_instance():
+    import paper_2405_02019_amd as P
+    return P.Instance(scale=1.0, seed=1)
+
+
+@pytest.mark.parametrize("engine", ["stepwise", "persistent"])
+def test_full_scale_window_bit_exact(P, full_oracle, engine):
     """Full-scale microcircuit (77,169 neurons, 2.99e8 synapses): the first
     300 steps match the oracle spike for spike, with the whole state."""
-    inst = P.Instance(scale=1.0, seed=1)
-    say("full scale: building GPU network")
-    with P.Simulator(inst) as sim:
+    say("full scale: building GPU network", engine)
+    with P.Simulator(oracle_stub_instance(), engine=engine) as sim:
         sim.step(300)
-        say("full scale: building oracle network")
-        net, osim = run_oracle(oracle, inst, 0, 300)
         say("full scale: comparing")
+        net, osim = full_oracle
         n = assert_parity(sim, 0, net, osim)
-        say("full scale spikes", n)
+        say("full scale spikes", n, sim.info())
