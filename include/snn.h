@@ -61,10 +61,14 @@ enum snn_syn_format {
 
 /* Step-loop engines. */
 enum snn_engine {
-  SNN_ENGINE_AUTO = 0,        /* persistent when it fits, else stepwise          */
+  SNN_ENGINE_AUTO = 0,        /* LDS when it fits, else persistent, else stepwise */
   SNN_ENGINE_STEPWISE = 1,    /* two kernels per step (update, then transfer)    */
-  SNN_ENGINE_PERSISTENT = 2   /* one cooperative kernel per chunk of steps, one
-                                 grid-wide barrier per step                       */
+  SNN_ENGINE_PERSISTENT = 2,  /* one cooperative kernel per chunk of steps, one
+                                 grid-wide barrier per step, ring in HBM          */
+  SNN_ENGINE_LDS = 3          /* persistent, each block owning 256 or 512 neurons
+                                 and their 64 ring rows in LDS; synapses stored
+                                 per (sender, destination block); needs the whole
+                                 network to fit the co-resident blocks            */
 };
 
 /* One microcircuit instance.  Defaults (snn_instance_default) are the

@@ -61,8 +61,16 @@ void parallel_for(int threads, F &&f) {
 
 }  // namespace
 
-int sample_instance(const snn_instance_cfg &cfg, uint32_t syn_format, int threads,
-                    HostInstance &out, std::string &err) {
+uint32_t instance_neurons(const snn_instance_cfg &cfg) {
+  uint32_t n_pop[8];
+  population_sizes(cfg.scale, n_pop);
+  uint32_t n = 0;
+  for (int p = 0; p < 8; ++p) n += n_pop[p];
+  return n;
+}
+
+int sample_instance(const snn_instance_cfg &cfg, uint32_t syn_format, uint32_t win_size,
+                    uint32_t win_origin, int threads, HostInstance &out, std::string &err) {
   if (!(cfg.scale > 0.0 && cfg.scale <= 64.0)) {
     err = "scale must lie in (0, 64]";
     return SNN_E_INVAL;
@@ -167,9 +175,22 @@ int sample_instance(const snn_instance_cfg &cfg, uint32_t syn_format, int thread
   out.nsyn = S;
 
   const bool comp = syn_format == SNN_SYN_COMPRESSED5;
-  const uint32_t nwin = comp ? ((out.n + (1u << kTargetBlockBits) - 1) >> kTargetBlockBits) : 1u;
+  if (win_size == 0 || (comp && win_size > (1u << kTargetBlockBits))) {
+    err = "target windows must hold 1 .. 65,536 neurons for 16-bit target offsets";
+    return SNN_E_RANGE;
+  }
+  const uint64_t wlo = uint64_t(win_origin) / win_size;
+  const uint64_t whi = (uint64_t(win_origin) + out.n - 1) / win_size;
+  const uint32_t nwin = uint32_t(whi - wlo + 1);
+  out.win_size = win_size;
+  out.win_origin = win_origin;
+  out.win_first = uint32_t(wlo);
   out.nwin = nwin;
   const uint64_t nseg = uint64_t(out.n) * nwin;
+  // target window of a receiver, relative to the instance's first window
+  auto window = [&](uint32_t post) {
+    return uint32_t((uint64_t(win_origin) + post) / win_size - wlo);
+  };
   const uint32_t key0 = uint32_t(cfg.seed), key1 = uint32_t(cfg.seed >> 32);
 
   // Thread ranges over the generation order.
@@ -199,7 +220,7 @@ int sample_instance(const snn_instance_cfg &cfg, uint32_t syn_format, int thread
       const Philox4 r = philox4x32_10(k, code, 0, kStreamSynapse, key0, key1);
       const uint32_t pre = pr.src0 + scale_word(r.v[0], pr.nsrc);
       const uint32_t post = pr.tgt0 + scale_word(r.v[1], pr.ntgt);
-      h[uint64_t(pre) * nwin + (comp ? (post >> kTargetBlockBits) : 0u)] += 1;
+      h[uint64_t(pre) * nwin + window(post)] += 1;
     }
   });
 
@@ -250,7 +271,7 @@ int sample_instance(const snn_instance_cfg &cfg, uint32_t syn_format, int thread
       if (pr.mu_w < 0.0 && w > 0.0) w = 0.0;
       const double dr = std::nearbyint(pr.mu_d + pr.sd_d * gauss(s.v[0], s.v[1]));
       const uint32_t d = dr < 1.0 ? 1u : (dr > double(kMaxDelay) ? uint32_t(kMaxDelay) : uint32_t(dr));
-      const uint64_t seg = uint64_t(pre) * nwin + (comp ? (post >> kTargetBlockBits) : 0u);
+      const uint64_t seg = uint64_t(pre) * nwin + window(post);
       const uint64_t pos = c[seg]++;
       int32_t wq;
       if (comp) {
@@ -259,7 +280,7 @@ int sample_instance(const snn_instance_cfg &cfg, uint32_t syn_format, int thread
           bad.store(2);
           continue;
         }
-        out.tgt16[pos] = uint16_t(post & ((1u << kTargetBlockBits) - 1u));
+        out.tgt16[pos] = uint16_t((uint64_t(win_origin) + post) % win_size);
         out.w16[pos] = int16_t(q);
         out.d8[pos] = uint8_t(d);
         wq = int32_t(q) * 8;

@@ -23,7 +23,9 @@ struct Control {
   uint64_t barrier;       // persistent kernel: arrivals at the grid barrier
   uint64_t exit_count;    // persistent kernel: blocks that have finished
   uint32_t lcnt[4];       // persistent: segment-list lengths, 3 rotating slots
-  uint64_t pad[2];
+  uint32_t epoch;         // LDS engine: barriers completed so far (flag epochs)
+  uint32_t pad32;
+  uint64_t pad[1];
 };
 
 // One storage segment of a sender, as published by the persistent engine for
@@ -63,6 +65,8 @@ struct DeviceNet {
   DevConsts *consts = nullptr;
   Control *ctl = nullptr;
   SegEntry *seg_list = nullptr;     // persistent: [3][ntot * nwin_max]
+  uint32_t lds_window = 0;          // LDS engine: neurons per block (256 or 512), else 0
+  uint32_t *flags = nullptr;        // LDS engine: per-block barrier epochs
 };
 
 struct LaunchShape {
@@ -84,5 +88,8 @@ hipError_t launch_persistent(const DeviceNet &d, const LaunchShape &sh, uint32_t
 // quad capacity per thread it was compiled for.
 int persistent_max_grid(const DeviceNet &d, uint32_t block, uint32_t qpt);
 uint32_t persistent_qmax(uint32_t qpt);
+// LDS engine: one cooperative launch of ntot / lds_window blocks runs n steps.
+hipError_t launch_lds(const DeviceNet &d, uint32_t n, hipStream_t s);
+int lds_max_grid(uint32_t window);
 
 }  // namespace snn

@@ -62,19 +62,11 @@ __device__ __forceinline__ void stage_tables(const DeviceNet &d, ThrTables &s) {
   for (uint32_t i = threadIdx.x; i < d.n_inst * 8; i += blockDim.x) s.meta[i] = d.pmeta[i];
 }
 
-template <bool LDS>
-__device__ __forceinline__ uint2 table_meta(const DeviceNet &d, const ThrTables &s, uint32_t idx) {
-  return LDS ? s.meta[idx] : d.pmeta[idx];
-}
-
-// T = #{k < len : u >= thr[off + k]} for a sorted table.  The first eight
-// entries are read unconditionally (tables are padded by 8), so the loads do
-// not depend on each other; longer counts (P ~ 1e-4 at the model's rates)
-// continue one entry at a time.
-template <bool LDS>
-__device__ __forceinline__ uint32_t thalamic_count(const DeviceNet &d, const ThrTables &s,
-                                                   uint2 m, uint32_t u) {
-  const uint32_t *tab = LDS ? s.thr : d.thr;
+// T = #{k < len : u >= thr[off + k]} for a sorted table (m = (off, len)).
+// The first eight entries are read unconditionally (tables are padded by 8),
+// so the loads do not depend on each other; longer counts (P ~ 1e-4 at the
+// model's rates) continue one entry at a time.
+__device__ __forceinline__ uint32_t thalamic_count(const uint32_t *tab, uint2 m, uint32_t u) {
   uint32_t T = 0;
 #pragma unroll
   for (uint32_t k = 0; k < 8; ++k) {
@@ -107,10 +99,10 @@ __device__ __forceinline__ uint32_t quad_code(const InstDev *__restrict__ ip, ui
 }
 
 // eqn:mem and eqn:ref for step t, with the thalamic counts T_t of the quad
-// (packed one byte per neuron into tp).  Returns a 4-bit spike mask.
-template <bool LDS>
-__device__ __forceinline__ uint32_t decide_quad(const DeviceNet &d, const ThrTables &s,
-                                                uint32_t inst, uint64_t seed, uint32_t lq,
+// (packed one byte per neuron into tp).  tab/meta hold the thalamic tables;
+// meta[mbase + population] = (offset, length).  Returns a 4-bit spike mask.
+__device__ __forceinline__ uint32_t decide_quad(const uint32_t *tab, const uint2 *meta,
+                                                uint32_t mbase, uint64_t seed, uint32_t lq,
                                                 uint32_t code, uint64_t t, Props k,
                                                 float (&u)[4], const float (&i)[4], uint32_t &r4,
                                                 uint32_t &tp, uint32_t &tsum) {
@@ -121,8 +113,8 @@ __device__ __forceinline__ uint32_t decide_quad(const DeviceNet &d, const ThrTab
   for (int m = 0; m < 4; ++m) {
     uint32_t r = (r4 >> (8 * m)) & 0xFFu;
     if ((code >> (12 + m)) & 1u) {
-      const uint2 meta = table_meta<LDS>(d, s, inst * 8u + ((code >> (3 * m)) & 7u));
-      const uint32_t T = thalamic_count<LDS>(d, s, meta, x.v[m]);
+      const uint2 mt = meta[mbase + ((code >> (3 * m)) & 7u)];
+      const uint32_t T = thalamic_count(tab, mt, x.v[m]);
       tpk |= T << (8 * m);
       tsum += T;
       if (r == 0) {
@@ -304,7 +296,8 @@ __global__ __launch_bounds__(BS) void k_update(DeviceNet d, uint32_t k_step) {
     const int32_t w[4] = {w4.x, w4.y, w4.z, w4.w};
     uint32_t r4 = d.R4[q], tp = 0;
     const uint32_t code = quad_code(ip, lq);
-    flags = decide_quad<LDS>(d, s_tab, inst, ip->seed, lq, code, t, k, u, i, r4, tp, tsum);
+    flags = decide_quad(LDS ? s_tab.thr : d.thr, LDS ? s_tab.meta : d.pmeta, inst * 8u, ip->seed,
+                        lq, code, t, k, u, i, r4, tp, tsum);
     const int32_t wext = ip->w_ext_q;
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
@@ -420,7 +413,7 @@ __global__ __launch_bounds__(BS) void k_transfer(DeviceNet d, uint32_t k_step) {
         }
         s_seg[s].start = st;
         s_seg[s].len = len[m];
-        s_seg[s].tbase = ip->gbase + (win << kTargetBlockBits);
+        s_seg[s].tbase = ip->tbase0 + win * ip->win_size;
       }
       mysum += len[m];
     }
@@ -651,8 +644,9 @@ __global__ __launch_bounds__(BS) void k_persistent(DeviceNet d, uint32_t n_steps
         if (uint32_t(j) < qpt && q < d.nquads) {
           const uint32_t inst = __builtin_amdgcn_readfirstlane(QI[j] >> 24);
           const InstDev *ip = d.inst + inst;
-          flags[j] = decide_quad<LDS>(d, s_tab, inst, ip->seed, QI[j] & 0xFFFFFFu, PC[j], t, k,
-                                      U[j], I[j], R[j], Tp[j], c_poi[j]);
+          flags[j] = decide_quad(LDS ? s_tab.thr : d.thr, LDS ? s_tab.meta : d.pmeta, inst * 8u,
+                                 ip->seed, QI[j] & 0xFFFFFFu, PC[j], t, k, U[j], I[j], R[j], Tp[j],
+                                 c_poi[j]);
         }
         uint32_t lo, tot;
         wave_compact(flags[j], lo, tot);
@@ -698,7 +692,7 @@ __global__ __launch_bounds__(BS) void k_persistent(DeviceNet d, uint32_t n_steps
               st = d.seg_ptr[sg + w];
               len = uint32_t(d.seg_ptr[sg + w + 1] - st);
             }
-            st_entry(dst + w, st, len, COMP ? ip->gbase + (w << kTargetBlockBits) : 0u);
+            st_entry(dst + w, st, len, COMP ? ip->tbase0 + w * ip->win_size : 0u);
           }
           const uint64_t pos = s_rbase + o;
           if (pos < d.raster_cap)
@@ -844,6 +838,374 @@ hipError_t launch_persistent(const DeviceNet &d, const LaunchShape &sh, uint32_t
   void *args[] = {&dv, &steps, &qpt, &spin};
   return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(fn), dim3(sh.grid),
                                     dim3(sh.block), args, 0, s);
+}
+
+
+// ---------------------------------------------------------------------------
+// LDS engine: the destination-partitioned form of the persistent loop.
+//
+// Block b owns the WN neurons [b WN, (b+1) WN) and their 64 ring rows, kept in
+// LDS for the whole chunk; the synapses are stored per (sender, destination
+// window), so each block delivers only its own segment of every sender's row
+// -- the paper's disjoint synapse classes by destination (Sec. 3.6), one class
+// per block -- with LDS atomics instead of device-scope ones.  Blocks share
+// only the per-step sender list (16-byte entries, device-coherent loads and
+// stores) and an epoch-flag grid barrier that uses no atomics: each block
+// stores its epoch into its own flag and polls all flags.
+//
+// The iteration structure is the persistent kernel's: (a) completes step t-1
+// from ring row t-1, (b) decides step t and publishes its senders, (c)
+// delivers step t-1's senders into rows t .. t+62.
+// ---------------------------------------------------------------------------
+constexpr uint32_t kLdsSeg = 512;
+
+struct SenderEntry {
+  uint32_t gid;        // global id of the sender
+  uint32_t segrow;     // its first storage segment
+  uint32_t win_first;  // global index of its instance's first target window
+  uint32_t nwin;       // target windows of its instance
+};
+
+__device__ __forceinline__ void st_sender(SegEntry *e, SenderEntry v) {
+  uint64_t *p = reinterpret_cast<uint64_t *>(e);
+  st_ag(p, uint64_t(v.gid) | (uint64_t(v.segrow) << 32));
+  st_ag(p + 1, uint64_t(v.win_first) | (uint64_t(v.nwin) << 32));
+}
+
+__device__ __forceinline__ SenderEntry ld_sender(const SegEntry *e) {
+  const uint64_t *p = reinterpret_cast<const uint64_t *>(e);
+  const uint64_t a = ld_ag(p), b = ld_ag(p + 1);
+  return SenderEntry{uint32_t(a), uint32_t(a >> 32), uint32_t(b), uint32_t(b >> 32)};
+}
+
+// Atomic-free grid barrier: flags[b] holds the last epoch block b reached.
+__device__ __forceinline__ bool flag_barrier(Control *ctl, uint32_t *flags, uint32_t G,
+                                             uint32_t epoch, uint32_t spin_limit,
+                                             uint32_t *s_flag) {
+  __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): this wave's stores are performed
+  __syncthreads();
+  if (threadIdx.x < 64) {
+    if (threadIdx.x == 0) st_ag(&flags[blockIdx.x], epoch);
+    uint32_t spins = 0;
+    bool ok = true;
+    for (;;) {
+      bool mine = true;
+      for (uint32_t i = __lane_id(); i < G; i += 64)
+        mine = mine && int32_t(ld_ag(&flags[i]) - epoch) >= 0;
+      if (__all(mine)) break;
+      __builtin_amdgcn_s_sleep(1);
+      if ((++spins & 63u) == 0 && (ld_ag(&ctl->error) != 0 || spins > spin_limit)) {
+        if (threadIdx.x == 0) st_ag(&ctl->error, 2u);
+        ok = false;
+        break;
+      }
+    }
+    if (threadIdx.x == 0) *s_flag = ok ? 1u : 0u;
+  }
+  __syncthreads();
+  return *s_flag != 0;
+}
+
+template <int WN, bool COMP>
+__global__ __launch_bounds__(256) void k_lds(DeviceNet d, uint32_t n_steps, uint32_t spin_limit) {
+  constexpr uint32_t BS = 256;
+  constexpr uint32_t NQ = WN / 4;          // quads of the window (one per thread)
+  constexpr uint32_t IPT = kLdsSeg / BS;
+  constexpr uint32_t TSTRIDE = kMaxPoisson + 8;
+  __shared__ int32_t s_ring[kRing * WN];
+  __shared__ uint32_t s_thr[2 * 8 * TSTRIDE];
+  __shared__ uint2 s_meta[16];
+  __shared__ SegStage s_seg[kLdsSeg];
+  __shared__ uint32_t s_excl[kLdsSeg];
+  __shared__ uint32_t s_tmp[BS / 64], s_wave[BS / 64];
+  __shared__ uint32_t s_base, s_flag, s_n, s_inst[2];
+  __shared__ unsigned long long s_rbase;
+
+  const uint32_t G = gridDim.x;
+  const uint32_t tid = threadIdx.x, wave = tid >> 6, lane = __lane_id();
+  const uint32_t wb0 = blockIdx.x * WN;
+  const uint32_t q = wb0 / 4 + tid;
+  const bool owner = tid < NQ && q < d.nquads;
+  const uint64_t t0 = d.ctl->t_base;
+  const uint32_t ep0 = d.ctl->epoch;
+  const Props k{d.consts->p11, d.consts->p22, d.consts->p21};
+  const size_t lstride = size_t(d.ntot);
+
+  // Ring rows of the window into LDS.
+  for (uint32_t i = tid; i < kRing * WN; i += BS) {
+    const uint32_t r = i / WN, c = i % WN;
+    s_ring[i] = wb0 + c < d.ntot ? d.W[size_t(r) * d.ntot + wb0 + c] : 0;
+  }
+  // Thalamic tables of the (at most two, 256-aligned) instances in the window.
+  if (tid < 2) {
+    const uint32_t qq = wb0 / 4 + tid * 64;
+    s_inst[tid] = qq < d.nquads ? d.qinfo[qq] >> 24 : 0xFFFFFFFFu;
+  }
+  __syncthreads();
+  if (tid < 16) {
+    const uint32_t slot = tid >> 3, p = tid & 7u;
+    const uint32_t inst = s_inst[slot];
+    uint2 m = make_uint2(0, 0);
+    if (inst != 0xFFFFFFFFu) m = d.pmeta[inst * 8 + p];
+    const uint32_t off = (slot * 8 + p) * TSTRIDE;
+    for (uint32_t kk = 0; kk < TSTRIDE; ++kk)
+      s_thr[off + kk] = kk < m.y ? d.thr[m.x + kk] : 0xFFFFFFFFu;
+    s_meta[slot * 8 + p] = make_uint2(off, m.y);
+  }
+
+  float U[4] = {0, 0, 0, 0}, I[4] = {0, 0, 0, 0};
+  uint32_t R = 0, Tp = 0, QI = 0, PC = 0, slot = 0, c_spk = 0, c_poi = 0;
+  int64_t c_con = 0;
+  uint64_t c_ev = 0, seed = 0;
+  int32_t wext = 0;
+  if (owner) {
+    const float4 uv = ld4(d.U + 4 * size_t(q));
+    const float4 iv = ld4(d.I + 4 * size_t(q));
+    U[0] = uv.x; U[1] = uv.y; U[2] = uv.z; U[3] = uv.w;
+    I[0] = iv.x; I[1] = iv.y; I[2] = iv.z; I[3] = iv.w;
+    R = d.R4[q];
+    QI = d.qinfo[q];
+    const InstDev *ip = d.inst + (QI >> 24);
+    PC = quad_code(ip, QI & 0xFFFFFFu);
+    seed = ip->seed;
+    wext = ip->w_ext_q;
+  }
+  __syncthreads();
+  if (owner) slot = (QI >> 24) == s_inst[0] ? 0u : 1u;
+
+  for (uint32_t it = 0; it <= n_steps; ++it) {
+    const uint64_t t = t0 + it;
+    const bool has_prev = it > 0;
+    const bool decide = it < n_steps;
+    SegEntry *lcur = d.seg_list + size_t(it % 3) * lstride;
+    const SegEntry *lprev = d.seg_list + size_t((it + 2) % 3) * lstride;
+
+    // (c) part 1: count of step t-1's senders and the first kSpec of them.
+    uint32_t nprev = 0;
+    SenderEntry spec{0, 0, 0, 0};
+    if (has_prev && wave == 0) {
+      nprev = ld_ag(&d.ctl->lcnt[(it + 2) % 3]);
+      spec = ld_sender(lprev + lane);
+    }
+    if (decide && blockIdx.x == 0 && tid == 0) st_ag(&d.ctl->lcnt[(it + 1) % 3], 0u);
+
+    // (a) complete step t-1 from ring row t-1 (LDS).
+    if (has_prev && owner) {
+      int32_t *row = s_ring + ((t - 1) & (kRing - 1)) * WN + 4 * tid;
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        const int32_t w = row[m];
+        row[m] = 0;
+        if ((PC >> (12 + m)) & 1u) {
+          I[m] = next_current(I[m], int32_t((Tp >> (8 * m)) & 0xFFu), wext, w, k.p11);
+          c_con += w;
+        }
+      }
+    }
+
+    // (b) decide step t and publish the senders.
+    if (decide) {
+      uint32_t flags = 0;
+      if (owner)
+        flags = decide_quad(s_thr, s_meta, slot * 8u, seed, QI & 0xFFFFFFu, PC, t, k, U, I, R, Tp,
+                            c_poi);
+      uint32_t lo, tot;
+      wave_compact(flags, lo, tot);
+      if (lane == 0) s_wave[wave] = tot;
+      __syncthreads();
+      if (tid == 0) {
+        uint32_t run = 0;
+        for (uint32_t w = 0; w < BS / 64; ++w) {
+          const uint32_t c = s_wave[w];
+          s_wave[w] = run;
+          run += c;
+        }
+        if (run) {
+          s_base = atomicAdd(&d.ctl->lcnt[it % 3], run);
+          s_rbase = atomicAdd(reinterpret_cast<unsigned long long *>(&d.ctl->raster_n),
+                              (unsigned long long)run);
+        }
+      }
+      __syncthreads();
+      if (flags) {
+        const InstDev *ip = d.inst + (QI >> 24);
+        const uint32_t lq = QI & 0xFFFFFFu;
+        uint32_t o = s_wave[wave] + lo;
+        c_spk += __popc(flags);
+        for (int m = 0; m < 4; ++m) {
+          if (!((flags >> m) & 1u)) continue;
+          const uint32_t gid = 4 * q + uint32_t(m);
+          const uint32_t segrow = ip->seg_base + (lq * 4u + uint32_t(m)) * ip->nwin;
+          st_sender(lcur + s_base + o, SenderEntry{gid, segrow, ip->win_first, ip->nwin});
+          c_ev += d.seg_ptr[segrow + ip->nwin] - d.seg_ptr[segrow];
+          const uint64_t pos = s_rbase + o;
+          if (pos < d.raster_cap)
+            d.raster[pos] = (t << 32) | gid;
+          else
+            d.ctl->overflow = 1;
+          ++o;
+        }
+      }
+    }
+
+    // (c) part 2: this block's segment of every sender of step t-1.
+    if (has_prev) {
+      if (tid == 0) s_n = nprev;
+      __syncthreads();
+      const uint32_t n = s_n;
+      for (uint32_t b0 = 0; b0 < n; b0 += kLdsSeg) {
+        const uint32_t nb = min(kLdsSeg, n - b0);
+        uint32_t len[IPT];
+#pragma unroll
+        for (uint32_t m = 0; m < IPT; ++m) {
+          const uint32_t s2 = m * BS + tid;
+          len[m] = 0;
+          if (s2 < nb) {
+            const SenderEntry e = (b0 == 0 && s2 < kSpec) ? spec : ld_sender(lprev + b0 + s2);
+            const uint32_t w = blockIdx.x - e.win_first;
+            uint64_t st = 0;
+            if (w < e.nwin) {
+              st = d.seg_ptr[e.segrow + w];
+              len[m] = uint32_t(d.seg_ptr[e.segrow + w + 1] - st);
+            }
+            s_seg[s2].start = st;
+            s_seg[s2].len = len[m];
+          }
+        }
+        // exclusive scan in s2 order: thread tid holds s2 = tid and tid + BS
+        uint32_t total0;
+        const uint32_t run0 = block_exclusive_scan<BS>(len[0], s_tmp, total0);
+        uint32_t total1;
+        const uint32_t run1 = block_exclusive_scan<BS>(IPT > 1 ? len[IPT - 1] : 0u, s_tmp, total1);
+        if (tid < nb) s_excl[tid] = run0;
+        if (IPT > 1 && BS + tid < nb) s_excl[BS + tid] = total0 + run1;
+        const uint32_t total = total0 + (IPT > 1 ? total1 : 0u);
+        __syncthreads();
+        constexpr int U8 = 8;
+        for (uint32_t e0 = tid; e0 < total; e0 += BS * U8) {
+          uint64_t idx[U8];
+#pragma unroll
+          for (int u = 0; u < U8; ++u) {
+            const uint32_t e = e0 + uint32_t(u) * BS;
+            idx[u] = ~0ull;
+            if (e < total) {
+              uint32_t lo2 = 0, hi2 = nb;
+              while (hi2 - lo2 > 1) {
+                const uint32_t mid = (lo2 + hi2) >> 1;
+                if (s_excl[mid] <= e) lo2 = mid; else hi2 = mid;
+              }
+              idx[u] = s_seg[lo2].start + (e - s_excl[lo2]);
+            }
+          }
+          uint32_t loc[U8], dl[U8];
+          int32_t wq[U8];
+#pragma unroll
+          for (int u = 0; u < U8; ++u) {
+            loc[u] = 0;
+            dl[u] = 0;
+            wq[u] = 0;
+            if (idx[u] != ~0ull) {
+              if (COMP) {
+                loc[u] = d.tgt16[idx[u]];
+                wq[u] = int32_t(d.w16[idx[u]]) * 8;
+                dl[u] = d.d8[idx[u]];
+              } else {
+                const uint64_t rec = d.rec8[idx[u]];
+                const uint32_t hiw = uint32_t(rec >> 32);
+                wq[u] = int32_t(uint32_t(rec));
+                loc[u] = (hiw >> 6) - wb0;
+                dl[u] = hiw & 63u;
+              }
+            }
+          }
+#pragma unroll
+          for (int u = 0; u < U8; ++u)
+            if (idx[u] != ~0ull)
+              atomicAdd(&s_ring[((t - 1 + dl[u]) & (kRing - 1)) * WN + loc[u]], wq[u]);
+        }
+        __syncthreads();
+      }
+    }
+
+    if (it == n_steps) break;
+    if (!flag_barrier(d.ctl, d.flags, G, ep0 + it + 1, spin_limit, &s_flag)) break;
+  }
+
+  // Ring rows, state and counters back to memory.
+  __syncthreads();
+  for (uint32_t i = tid; i < kRing * WN; i += BS) {
+    const uint32_t r = i / WN, c = i % WN;
+    if (wb0 + c < d.ntot) d.W[size_t(r) * d.ntot + wb0 + c] = s_ring[i];
+  }
+  if (owner) {
+    *reinterpret_cast<float4 *>(d.U + 4 * size_t(q)) = make_float4(U[0], U[1], U[2], U[3]);
+    *reinterpret_cast<float4 *>(d.I + 4 * size_t(q)) = make_float4(I[0], I[1], I[2], I[3]);
+    d.R4[q] = R;
+  }
+  {
+    uint64_t sp = c_spk, po = c_poi, ev = c_ev;
+    int64_t co = c_con;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      sp += __shfl_xor(sp, o);
+      po += __shfl_xor(po, o);
+      ev += __shfl_xor(ev, o);
+      co += __shfl_xor(co, o);
+    }
+    if (lane == 0 && tid < NQ && q < d.nquads) {
+      int64_t *c = d.wave_ctr + 4 * size_t(q >> 6);
+      c[0] += int64_t(sp);
+      c[1] += int64_t(po);
+      c[2] += co;
+      c[3] += int64_t(ev);
+    }
+  }
+  __builtin_amdgcn_s_waitcnt(0x0F70);
+  __syncthreads();
+  if (tid == 0) {
+    const uint64_t done =
+        __hip_atomic_fetch_add(&d.ctl->exit_count, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (done == G - 1) {
+      st_ag(&d.ctl->lcnt[0], 0u);
+      st_ag(&d.ctl->lcnt[1], 0u);
+      st_ag(&d.ctl->lcnt[2], 0u);
+      st_ag(&d.ctl->exit_count, 0ull);
+      st_ag(&d.ctl->epoch, ep0 + n_steps);
+      st_ag(&d.ctl->t_base, t0 + n_steps);
+    }
+  }
+}
+
+using LdsFn = void (*)(DeviceNet, uint32_t, uint32_t);
+
+static LdsFn lds_fn(uint32_t window, bool comp) {
+  if (window == 512) return comp ? k_lds<512, true> : k_lds<512, false>;
+  if (window == 256) return comp ? k_lds<256, true> : k_lds<256, false>;
+  return nullptr;
+}
+
+int lds_max_grid(uint32_t window) {
+  LdsFn fn = lds_fn(window, false);
+  if (!fn) return 0;
+  int per_cu = 0, dev = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(fn), 256,
+                                                   0) != hipSuccess)
+    return 0;
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return 0;
+  return per_cu * prop.multiProcessorCount;
+}
+
+hipError_t launch_lds(const DeviceNet &d, uint32_t n, hipStream_t s) {
+  LdsFn fn = lds_fn(d.lds_window, d.syn_format == SNN_SYN_COMPRESSED5);
+  if (!fn) return hipErrorInvalidConfiguration;
+  const uint32_t grid = (d.ntot + d.lds_window - 1) / d.lds_window;
+  DeviceNet dv = d;
+  uint32_t steps = n;
+  uint32_t spin = 1u << 24;
+  void *args[] = {&dv, &steps, &spin};
+  return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(fn), dim3(grid), dim3(256), args,
+                                    0, s);
 }
 
 }  // namespace snn

@@ -137,6 +137,24 @@ uint64_t spike_bound(const snn_net *h, uint64_t steps) {
   return h->n_real * ((steps + kRefSteps) / (kRefSteps + 1));
 }
 
+// LDS engine: block b owns neurons [b W, (b+1) W) with their 64 ring rows in
+// LDS.  W = 512 (one block per CU) when the network fits, else W = 256 (two
+// blocks per CU); 0 when neither fits the co-resident grid.
+uint32_t lds_capacity() {
+  const int g512 = lds_max_grid(512), g256 = lds_max_grid(256);
+  return uint32_t(std::max(int64_t(g512) * 512, int64_t(g256) * 256));
+}
+
+uint32_t choose_lds_window(uint32_t ntot, uint32_t block, uint32_t grid) {
+  if (block && block != 256) return 0;
+  for (uint32_t w : {512u, 256u}) {
+    const uint32_t g = (ntot + w - 1) / w;
+    if (grid && grid != g) continue;
+    if (int64_t(g) <= int64_t(lds_max_grid(w))) return w;
+  }
+  return 0;
+}
+
 // Persistent grid: 4 neurons per quad, `qpt` quads per thread, at most the
 // co-resident block count of the kernel.  Fewer blocks make the per-step grid
 // barrier cheaper; more threads give the transfer phase more parallelism.
@@ -162,6 +180,10 @@ int choose_persistent_shape(snn_net *h, uint32_t block, uint32_t grid) {
 }
 
 int queue_steps(snn_net *h, uint32_t n) {
+  if (h->engine == SNN_ENGINE_LDS) {
+    HIP_OK(h, launch_lds(h->d, n, h->stream));
+    return SNN_OK;
+  }
   if (h->engine == SNN_ENGINE_PERSISTENT) {
     HIP_OK(h, launch_persistent(h->d, h->shape, n, h->stream));
     return SNN_OK;
@@ -226,7 +248,7 @@ int snn_build(const snn_config *cfg, snn_net **out) {
     return fail(nullptr, SNN_E_INVAL, "need 1..%u instances", kMaxInstances);
   if (cfg->syn_format > SNN_SYN_COMPRESSED5)
     return fail(nullptr, SNN_E_INVAL, "unknown synapse format %u", cfg->syn_format);
-  if (cfg->engine > SNN_ENGINE_PERSISTENT)
+  if (cfg->engine > SNN_ENGINE_LDS)
     return fail(nullptr, SNN_E_INVAL, "unknown engine %u", cfg->engine);
   const auto t_start = std::chrono::steady_clock::now();
 
@@ -240,32 +262,66 @@ int snn_build(const snn_config *cfg, snn_net **out) {
     return rc;
   };
 
-  // ---- sample every instance on the host ----
+  // ---- placement (before sampling: the storage layout depends on it) ----
   const uint32_t ni = cfg->n_instances;
-  std::vector<HostInstance> hi(ni);
   h->im.resize(ni);
-  uint32_t gbase = 0, nwin_max = 1;
-  uint64_t nseg_tot = 0, nsyn_tot = 0, nthr = 0;
+  uint32_t gbase = 0;
   for (uint32_t k = 0; k < ni; ++k) {
-    std::string e;
-    int rc = sample_instance(cfg->inst[k], cfg->syn_format, cfg->host_threads, hi[k], e);
-    if (rc) {
-      fail(h, rc, "instance %u: %s", k, e.c_str());
-      return bail(rc);
-    }
     InstMeta &m = h->im[k];
-    m.n = hi[k].n;
+    m.n = instance_neurons(cfg->inst[k]);
+    if (m.n == 0 || m.n >= (1u << 26)) {
+      fail(h, SNN_E_INVAL, "instance %u: scale %g gives %u neurons", k, cfg->inst[k].scale, m.n);
+      return bail(SNN_E_INVAL);
+    }
     m.npad = (m.n + kInstAlign - 1) / kInstAlign * kInstAlign;
     m.gbase = gbase;
-    std::memcpy(m.pop_off, hi[k].pop_off, sizeof m.pop_off);
-    m.nsyn = hi[k].nsyn;
-    m.w_f = hi[k].w_f;
-    m.w_ext_q = hi[k].w_ext_q;
     if (uint64_t(gbase) + m.npad >= (1ull << 26)) {
       fail(h, SNN_E_RANGE, "more than 2^26 neurons in total");
       return bail(SNN_E_RANGE);
     }
     gbase += m.npad;
+  }
+  const uint32_t ntot = gbase;
+
+  // ---- engine: the LDS-resident ring needs its whole network in the
+  // aggregate LDS (one 512- or 256-neuron window per co-resident block) ----
+  h->engine = cfg->engine == SNN_ENGINE_AUTO ? SNN_ENGINE_LDS : cfg->engine;
+  uint32_t lds_window = 0;
+  if (h->engine == SNN_ENGINE_LDS) {
+    lds_window = choose_lds_window(ntot, cfg->block_size, cfg->grid_blocks);
+    if (!lds_window) {
+      if (cfg->engine == SNN_ENGINE_LDS) {
+        fail(h, SNN_E_RANGE, "the LDS engine holds at most %u neurons on this device", lds_capacity());
+        return bail(SNN_E_RANGE);
+      }
+      h->engine = SNN_ENGINE_PERSISTENT;
+    }
+  }
+
+  // ---- sample every instance on the host ----
+  std::vector<HostInstance> hi(ni);
+  uint32_t nwin_max = 1;
+  uint64_t nseg_tot = 0, nsyn_tot = 0, nthr = 0;
+  for (uint32_t k = 0; k < ni; ++k) {
+    InstMeta &m = h->im[k];
+    uint32_t wsize = kNoWindows, worigin = 0;
+    if (lds_window) {
+      wsize = lds_window;
+      worigin = m.gbase;
+    } else if (cfg->syn_format == SNN_SYN_COMPRESSED5) {
+      wsize = 1u << kTargetBlockBits;
+    }
+    std::string e;
+    int rc = sample_instance(cfg->inst[k], cfg->syn_format, wsize, worigin, cfg->host_threads,
+                             hi[k], e);
+    if (rc) {
+      fail(h, rc, "instance %u: %s", k, e.c_str());
+      return bail(rc);
+    }
+    std::memcpy(m.pop_off, hi[k].pop_off, sizeof m.pop_off);
+    m.nsyn = hi[k].nsyn;
+    m.w_f = hi[k].w_f;
+    m.w_ext_q = hi[k].w_ext_q;
     nwin_max = std::max(nwin_max, hi[k].nwin);
     nseg_tot += uint64_t(m.n) * hi[k].nwin;
     nsyn_tot += m.nsyn;
@@ -274,8 +330,9 @@ int snn_build(const snn_config *cfg, snn_net **out) {
   }
   DeviceNet &d = h->d;
   d.n_inst = ni;
-  d.ntot = gbase;
-  d.nquads = gbase / 4;
+  d.ntot = ntot;
+  d.nquads = ntot / 4;
+  d.lds_window = lds_window;
   d.nwin_max = nwin_max;
   d.syn_format = cfg->syn_format;
 
@@ -331,8 +388,9 @@ int snn_build(const snn_config *cfg, snn_net **out) {
   ALLOC(d.events, ni);
   ALLOC(d.consts, 1);
   ALLOC(d.ctl, 1);
-  const bool want_persistent = cfg->engine != SNN_ENGINE_STEPWISE;
+  const bool want_persistent = h->engine != SNN_ENGINE_STEPWISE;
   if (want_persistent) ALLOC(d.seg_list, 3 * size_t(d.ntot) * nwin_max);
+  if (lds_window) ALLOC(d.flags, (d.ntot + lds_window - 1) / lds_window);
 #undef ALLOC
 
   // ---- host staging and upload ----
@@ -363,6 +421,9 @@ int snn_build(const snn_config *cfg, snn_net **out) {
     }
     v.seg_base = uint32_t(seg.size());
     v.nwin = x.nwin;
+    v.win_first = x.win_first;
+    v.win_size = x.win_size;
+    v.tbase0 = uint32_t(uint64_t(m.gbase) + uint64_t(x.win_first) * x.win_size - x.win_origin);
     for (uint32_t lq = 0; lq < m.npad / 4; ++lq) qinfo[m.gbase / 4 + lq] = (k << 24) | lq;
     std::copy(x.u0.begin(), x.u0.end(), u0.begin() + m.gbase);
     for (uint64_t s = 0; s + 1 < x.seg_ptr.size(); ++s) seg.push_back(syn_base + x.seg_ptr[s]);
@@ -425,7 +486,8 @@ int snn_build(const snn_config *cfg, snn_net **out) {
       hipMemset(d.spk_list, 0, 2 * size_t(d.ntot) * sizeof(uint32_t)) != hipSuccess ||
       hipMemset(d.wave_ctr, 0, 4 * size_t(d.nquads / 64) * sizeof(int64_t)) != hipSuccess ||
       hipMemset(d.events, 0, ni * sizeof(uint64_t)) != hipSuccess ||
-      hipMemset(d.ctl, 0, sizeof(Control)) != hipSuccess) {
+      hipMemset(d.ctl, 0, sizeof(Control)) != hipSuccess ||
+      (d.flags && hipMemset(d.flags, 0, ((d.ntot + lds_window - 1) / lds_window) * sizeof(uint32_t)) != hipSuccess)) {
     fail(h, SNN_E_HIP, "device memset failed");
     return bail(SNN_E_HIP);
   }
@@ -438,13 +500,15 @@ int snn_build(const snn_config *cfg, snn_net **out) {
   // ---- engine ----
   h->shape.block = 256;
   h->shape.scatter_blocks = 1024;
-  h->engine = SNN_ENGINE_STEPWISE;
-  if (want_persistent) {
+  if (h->engine == SNN_ENGINE_LDS) {
+    h->shape.block = 256;
+    h->shape.grid = (d.ntot + lds_window - 1) / lds_window;
+    h->shape.qpt = 1;
+  } else if (h->engine == SNN_ENGINE_PERSISTENT) {
     int rc2 = choose_persistent_shape(h, cfg->block_size, cfg->grid_blocks);
-    if (rc2 == SNN_OK) {
-      h->engine = SNN_ENGINE_PERSISTENT;
-    } else if (cfg->engine == SNN_ENGINE_PERSISTENT) {
-      return bail(rc2);
+    if (rc2 != SNN_OK) {
+      if (cfg->engine == SNN_ENGINE_PERSISTENT) return bail(rc2);
+      h->engine = SNN_ENGINE_STEPWISE;
     }
   }
   if (h->engine == SNN_ENGINE_STEPWISE) {
@@ -578,7 +642,7 @@ int snn_get_info(const snn_net *h, snn_info *out) {
   std::memset(out, 0, sizeof *out);
   out->engine = h->engine;
   out->block_size = h->shape.block;
-  out->grid_blocks = h->engine == SNN_ENGINE_PERSISTENT ? h->shape.grid : h->shape.scatter_blocks;
+  out->grid_blocks = h->engine == SNN_ENGINE_STEPWISE ? h->shape.scatter_blocks : h->shape.grid;
   out->quads_per_thread = h->shape.qpt;
   out->chunk_steps = h->chunk;
   out->n_neurons_total = h->d.ntot;
@@ -618,7 +682,8 @@ int snn_sample_network(const snn_instance_cfg *inst, uint32_t syn_format, int32_
   *out = nullptr;
   HostInstance x;
   std::string e;
-  int rc = sample_instance(*inst, syn_format, host_threads, x, e);
+  const uint32_t wsize = syn_format == SNN_SYN_COMPRESSED5 ? (1u << kTargetBlockBits) : kNoWindows;
+  int rc = sample_instance(*inst, syn_format, wsize, 0, host_threads, x, e);
   if (rc) return fail(nullptr, rc, "%s", e.c_str());
   snn_host_network *n = static_cast<snn_host_network *>(std::calloc(1, sizeof(snn_host_network)));
   if (!n) return fail(nullptr, SNN_E_NOMEM, "host allocation failed");
@@ -642,7 +707,7 @@ int snn_sample_network(const snn_instance_cfg *inst, uint32_t syn_format, int32_
       const uint64_t s = uint64_t(i) * x.nwin + w;
       for (uint64_t e2 = x.seg_ptr[s]; e2 < x.seg_ptr[s + 1]; ++e2) {
         if (comp) {
-          n->post[e2] = (w << kTargetBlockBits) + x.tgt16[e2];
+          n->post[e2] = (x.win_first + w) * x.win_size + x.tgt16[e2] - x.win_origin;
           n->delay[e2] = x.d8[e2];
           n->w_q[e2] = int32_t(x.w16[e2]) * 8;
         } else {

@@ -28,6 +28,7 @@ constexpr float kTheta = 15.0f;
 // wavefront never mixes two instances.
 constexpr uint32_t kInstAlign = 256;
 constexpr uint32_t kTargetBlockBits = 16;  // compressed targets: 16-bit offsets
+constexpr uint32_t kNoWindows = 1u << 26;   // window size meaning "one segment per sender"
 constexpr int kMaxPoisson = 64;            // longest thalamic table
 constexpr uint32_t kMaxInstances = 256;
 
@@ -74,7 +75,10 @@ struct InstDev {
   uint32_t thr_off[8];   // first threshold of each population in the table
   uint32_t thr_len[8];
   uint32_t seg_base;     // first segment of the instance
-  uint32_t nwin;         // segments per neuron (target blocks; 1 for plain)
+  uint32_t nwin;         // segments per sender: target windows the instance overlaps
+  uint32_t win_first;    // global index of the first of those windows
+  uint32_t win_size;     // neurons per target window
+  uint32_t tbase0;       // global id of the first target of window 0 of the instance
 };
 
 // FP32 propagators, computed in FP64 on the device (eqn:p11p22, eqn:p21).
@@ -96,7 +100,10 @@ struct HostInstance {
   uint32_t thr[8][kMaxPoisson] = {};
   uint32_t thr_len[8] = {};
   std::vector<float> u0;
-  // Storage: segments [n * nwin + 1] into the record streams.
+  // Storage: one segment per (sender, target window); windows of win_size
+  // neurons are aligned at multiples of win_size in the coordinate
+  // win_origin + local id; [n * nwin + 1] pointers into the record streams.
+  uint32_t win_size = 0, win_origin = 0, win_first = 0;
   uint32_t nwin = 1;
   std::vector<uint64_t> seg_ptr;
   std::vector<uint64_t> rec8;        // plain: w_q | (target << 6 | delay) << 32
@@ -118,9 +125,14 @@ std::vector<double> connectivity(const snn_instance_cfg &cfg);
 extern const uint32_t kPopFull[8];
 extern const uint32_t kKext[8];
 
-// Sampler (builder.cpp).  Targets are instance-local ids; the runtime offsets
-// plain records by the instance's first global id when it uploads them.
-int sample_instance(const snn_instance_cfg &cfg, uint32_t syn_format, int threads,
-                    HostInstance &out, std::string &err);
+// Sampler (builder.cpp).  Rows are split into target windows of win_size
+// neurons aligned in the coordinate win_origin + local id (win_size >= 2^26:
+// one segment per sender).  Plain records hold instance-local targets (the
+// runtime offsets them by the instance's first global id on upload);
+// compressed records hold the target's offset inside its window (< 2^16).
+int sample_instance(const snn_instance_cfg &cfg, uint32_t syn_format, uint32_t win_size,
+                    uint32_t win_origin, int threads, HostInstance &out, std::string &err);
+// Population sizes of an instance (for placement before sampling).
+uint32_t instance_neurons(const snn_instance_cfg &cfg);
 
 }  // namespace snn

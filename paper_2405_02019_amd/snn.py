@@ -20,6 +20,7 @@ SYN_COMPRESSED5 = 1
 ENGINE_AUTO = 0
 ENGINE_STEPWISE = 1
 ENGINE_PERSISTENT = 2
+ENGINE_LDS = 3
 ABI_VERSION = 1
 
 SNN_OK = 0
@@ -163,7 +164,8 @@ def _syn_format(fmt):
 
 def _engine(e):
     if isinstance(e, str):
-        return {"auto": ENGINE_AUTO, "stepwise": ENGINE_STEPWISE, "persistent": ENGINE_PERSISTENT}[e]
+        return {"auto": ENGINE_AUTO, "stepwise": ENGINE_STEPWISE, "persistent": ENGINE_PERSISTENT,
+                "lds": ENGINE_LDS}[e]
     return int(e)
 
 

@@ -71,7 +71,7 @@ def test_propagators_on_gpu(P, oracle):
     assert st["w_ext_q"] == k["w_ext_q"] and st["w_f"] == k["w_f"]
 
 
-@pytest.mark.parametrize("engine", ["stepwise", "persistent"])
+@pytest.mark.parametrize("engine", ["stepwise", "persistent", "lds"])
 @pytest.mark.parametrize("fmt,wmode", [("plain", 0), ("compressed", 1)])
 def test_tiny_circuit_bit_exact(P, oracle, engine, fmt, wmode):
     """1 % circuit (772 neurons), 0.1 s of biological time in ragged pieces
@@ -115,6 +115,22 @@ def test_persistent_shapes(P, oracle, scale, block, grid, chunk):
         assert_parity(sim, 0, net, osim)
 
 
+@pytest.mark.parametrize("grid", [8, 16])
+@pytest.mark.parametrize("fmt,wmode", [("plain", 0), ("compressed", 1)])
+def test_lds_windows(P, oracle, grid, fmt, wmode):
+    """LDS engine with 512-neuron (8 blocks) and 256-neuron (16 blocks)
+    windows on the 5 % circuit (3,859 neurons, 0.75 M synapses)."""
+    inst = P.Instance(scale=0.05, seed=31)
+    say("lds windows", grid, fmt)
+    with P.Simulator(inst, syn_format=fmt, engine="lds", grid_blocks=grid, chunk_steps=37) as sim:
+        info = sim.info()
+        assert info["engine"] == P.ENGINE_LDS and info["grid_blocks"] == grid
+        sim.step(150)
+        sim.step(100)
+        net, osim = run_oracle(oracle, inst, wmode, 250)
+        assert_parity(sim, 0, net, osim)
+
+
 def test_degenerate_drives(P, oracle):
     """No synapses and no thalamic input; then a constant count of one
     thalamic spike per step at a sub-threshold amplitude; then no drive at
@@ -123,7 +139,7 @@ def test_degenerate_drives(P, oracle):
              P.Instance(scale=0.01, seed=3, bg_const_T=1, psp_ext_mv=0.07),
              P.Instance(scale=0.01, seed=4, bg_rate_hz=0.0)]
     for inst in cases:
-      for engine in ["stepwise", "persistent"]:
+      for engine in ["stepwise", "persistent", "lds"]:
         say("degenerate", engine, inst)
         with P.Simulator(inst, engine=engine) as sim:
             sim.step(250)
@@ -139,7 +155,7 @@ def test_batched_instances_each_bit_exact(P, oracle):
              P.Instance(scale=0.013, seed=13, g=-3.5, bg_rate_hz=6.5, indegree_mode=1),
              P.Instance(scale=0.002, seed=14)]
     for fmt, wmode in [("plain", 0), ("compressed", 1)]:
-      for engine in ["stepwise", "persistent"]:
+      for engine in ["stepwise", "persistent", "lds"]:
         say("batch", fmt, engine)
         with P.Simulator(insts, syn_format=fmt, engine=engine) as sim:
             sim.step(400)
@@ -160,7 +176,7 @@ def oracle_stub_instance():
     return P.Instance(scale=1.0, seed=1)
 
 
-@pytest.mark.parametrize("engine", ["stepwise", "persistent"])
+@pytest.mark.parametrize("engine", ["stepwise", "persistent", "lds"])
 def test_full_scale_window_bit_exact(P, full_oracle, engine):
     """Full-scale microcircuit (77,169 neurons, 2.99e8 synapses): the first
     300 steps match the oracle spike for spike, with the whole state."""
