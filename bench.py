@@ -61,7 +61,8 @@ def run_leg(P, fmt, engine, warm_bio_s, timed_bio_s, log):
     rec = 8.0 if fmt == "plain" else 5.0
     ring_b, syn_b = algorithmic_bytes(n, spikes, events, rec)
     total_bytes = ring_b * n_steps + syn_b
-    launches = -(-n_steps // info["chunk_steps"]) if info["engine"] == P.ENGINE_PERSISTENT else 2 * n_steps
+    chunked = info["engine"] in (P.ENGINE_PERSISTENT, P.ENGINE_LDS)
+    launches = -(-n_steps // info["chunk_steps"]) if chunked else 2 * n_steps
     sim.close()
     return {
         "fmt": fmt, "wall_s": wall, "gpu_ms": gpu_ms, "events": events, "spikes": spikes,
@@ -70,13 +71,23 @@ def run_leg(P, fmt, engine, warm_bio_s, timed_bio_s, log):
     }
 
 
-def measured_traffic(fmt, engine_is_persistent):
+def kernel_name(P, info):
+    """Name of the dominant kernel of an engine (as rocprofv3 lists it)."""
+    e = info["engine"]
+    if e == P.ENGINE_LDS:
+        return "k_lds"
+    if e == P.ENGINE_PERSISTENT:
+        return "k_persistent"
+    return "k_update + k_transfer"
+
+
+def measured_traffic(kernel, fmt):
     """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE
     summary, scaled by the copy calibration -- only while the kernel source is
     the one the counters were taken on."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "traffic_k_persistent_full_scale_plain.json")
-    if fmt != "plain" or not engine_is_persistent or not os.path.exists(path):
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_full_scale_{fmt}.json")
+    if not os.path.exists(path):
         return None
     rec = json.load(open(path))
     src = os.path.join(ROOT, "paper_2405_02019_amd", "csrc", "kernels.hip")
@@ -121,7 +132,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10, help="timed seconds of biological time")
     ap.add_argument("--warmup", type=int, default=1, help="untimed seconds of biological time")
-    ap.add_argument("--engine", default="auto", choices=["auto", "stepwise", "persistent"])
+    ap.add_argument("--engine", default="auto", choices=["auto", "stepwise", "persistent", "lds"])
     ap.add_argument("--no-compressed", action="store_true", help="skip the compressed-synapse leg")
     ap.add_argument("--cpu-steps", type=int, default=4000,
                     help="oracle steps for the CPU baseline (0 = skip)")
@@ -155,8 +166,10 @@ def main():
     value = plain["events"] / plain["wall_s"]
     avg_launch_ms = plain["gpu_ms"] / plain["launches"]
     achieved = plain["bytes"] / plain["launches"] / (avg_launch_ms * 1e-3) / 1e9
-    kernel = ("k_persistent (one cooperative launch per chunk of %d steps)" % plain["info"]["chunk_steps"]
-              if plain["info"]["engine"] == P.ENGINE_PERSISTENT else "k_update + k_transfer")
+    kname = kernel_name(P, plain["info"])
+    kernel = kname
+    if plain["info"]["engine"] in (P.ENGINE_PERSISTENT, P.ENGINE_LDS):
+        kernel += " (one cooperative launch per chunk of %d steps)" % plain["info"]["chunk_steps"]
     out = {
         "metric": "realtime factor & synaptic events/s, full PD microcircuit; plain vs compressed",
         "value": value,
@@ -183,7 +196,7 @@ def main():
         "build_s": plain["build_s"],
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic("plain", plain["info"]["engine"] == P.ENGINE_PERSISTENT),
+                     "traffic": measured_traffic(kname, "plain"),
                      "kernel": kernel,
                      "avg_launch_ms": avg_launch_ms,
                      "bytes_per_launch": plain["bytes"] / plain["launches"]},

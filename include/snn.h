@@ -231,6 +231,18 @@ typedef struct {
  */
 int snn_sample_network(const snn_instance_cfg *inst, uint32_t syn_format, int32_t host_threads,
                        snn_host_network **out);
+
+/*
+ * snn_sample_network_windows -- as snn_sample_network, but stored in the
+ * layout of the LDS engine with `window`-neuron target windows (256 or 512):
+ * per (sender, window) a segment of fixed capacity, the largest segment of
+ * the sender's population in that window (Sec. 3.6's synapse classes by
+ * destination), read back into rows ordered by window.  window = 0 gives
+ * snn_sample_network.  Errors: SNN_E_INVAL for another window; as
+ * snn_sample_network otherwise.
+ */
+int snn_sample_network_windows(const snn_instance_cfg *inst, uint32_t syn_format, uint32_t window,
+                               int32_t host_threads, snn_host_network **out);
 void snn_free_network(snn_host_network *net);
 
 #ifdef __cplusplus

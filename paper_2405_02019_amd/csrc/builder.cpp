@@ -8,8 +8,13 @@
 // any number of threads in two passes over the generation order
 // (b, a, k): pass 1 counts synapses per storage segment and thread, a prefix
 // sum turns the counts into per-thread write cursors, and pass 2 regenerates
-// every synapse and writes it at its cursor.  Rows keep generation order, so
-// the result does not depend on the thread count.
+// every synapse and writes it at its cursor.  Segments keep generation order,
+// so the result does not depend on the thread count.
+//
+// Two layouts: compact segments addressed through a pointer array (sender
+// rows, optionally split by target window), or fixed-capacity segments per
+// (sender, window) whose capacity is the largest segment of the sender's
+// population in that window, so the address is computable from the sender.
 //
 // Model readings: weights Normal(mu, 0.1 |mu|) with mu = w_f * PSP,
 // PSP = 0.15 mV (excitatory sender), g * 0.15 mV (inhibitory sender), 0.30 mV
@@ -69,8 +74,21 @@ uint32_t instance_neurons(const snn_instance_cfg &cfg) {
   return n;
 }
 
+uint32_t thalamic_table_max(const snn_instance_cfg &cfg) {
+  if (cfg.bg_const_T >= 0) return uint32_t(cfg.bg_const_T);
+  uint32_t m = 0, thr[kMaxPoisson], len = 0;
+  std::string err;
+  for (int p = 0; p < 8; ++p) {
+    const double lam = (cfg.bg_rate_hz * double(kKext[p])) * 1e-4;
+    if (poisson_thresholds(lam, thr, kMaxPoisson, &len, err) != SNN_OK) return kMaxPoisson + 1;
+    m = std::max(m, len);
+  }
+  return m;
+}
+
 int sample_instance(const snn_instance_cfg &cfg, uint32_t syn_format, uint32_t win_size,
-                    uint32_t win_origin, int threads, HostInstance &out, std::string &err) {
+                    uint32_t win_origin, bool pad, int threads, HostInstance &out,
+                    std::string &err) {
   if (!(cfg.scale > 0.0 && cfg.scale <= 64.0)) {
     err = "scale must lie in (0, 64]";
     return SNN_E_INVAL;
@@ -224,9 +242,15 @@ int sample_instance(const snn_instance_cfg &cfg, uint32_t syn_format, uint32_t w
     }
   });
 
-  // Segment pointers and per-thread cursors (segment-major, thread-minor).
-  out.seg_ptr.assign(nseg + 1, 0);
-  {
+  auto seg_len = [&](uint64_t s) {
+    uint64_t c = 0;
+    for (int t = 0; t < P; ++t) c += cur[t][s];
+    return c;
+  };
+  out.padded = pad;
+  if (!pad) {
+    // Segment pointers and per-thread cursors (segment-major, thread-minor).
+    out.seg_ptr.assign(nseg + 1, 0);
     uint64_t run = 0;
     for (uint64_t s = 0; s < nseg; ++s) {
       out.seg_ptr[s] = run;
@@ -237,15 +261,52 @@ int sample_instance(const snn_instance_cfg &cfg, uint32_t syn_format, uint32_t w
       }
     }
     out.seg_ptr[nseg] = run;
+    out.nrec = run;
+  } else {
+    // Fixed-capacity segments: every sender of population c owns cap[w][c]
+    // record slots in window w, so a segment's address follows from the
+    // sender's id alone; unused slots keep delay 0.
+    out.seg_ptr.clear();
+    out.cls_cap.assign(size_t(nwin) * 8, 0);
+    out.cls_base.assign(size_t(nwin) * 8, 0);
+    out.outdeg.assign(out.n, 0);
+    for (int c = 0; c < 8; ++c)
+      for (uint32_t pre = out.pop_off[c]; pre < out.pop_off[c + 1]; ++pre)
+        for (uint32_t w = 0; w < nwin; ++w) {
+          const uint64_t len = seg_len(uint64_t(pre) * nwin + w);
+          out.outdeg[pre] += uint32_t(len);
+          uint32_t &cp = out.cls_cap[size_t(w) * 8 + c];
+          if (len > cp) cp = uint32_t(len);
+        }
+    uint64_t run = 0;
+    for (uint32_t w = 0; w < nwin; ++w)
+      for (int c = 0; c < 8; ++c) {
+        out.cls_base[size_t(w) * 8 + c] = run;
+        run += uint64_t(n_pop[c]) * out.cls_cap[size_t(w) * 8 + c];
+      }
+    out.nrec = run;
+    for (int c = 0; c < 8; ++c)
+      for (uint32_t pre = out.pop_off[c]; pre < out.pop_off[c + 1]; ++pre)
+        for (uint32_t w = 0; w < nwin; ++w) {
+          const uint64_t s = uint64_t(pre) * nwin + w;
+          uint64_t at = out.cls_base[size_t(w) * 8 + c] +
+                        uint64_t(pre - out.pop_off[c]) * out.cls_cap[size_t(w) * 8 + c];
+          for (int t = 0; t < P; ++t) {
+            const uint64_t cnt = cur[t][s];
+            cur[t][s] = at;
+            at += cnt;
+          }
+        }
   }
 
+  const uint64_t R = out.nrec;
   if (comp) {
     out.rec8.clear();
-    out.tgt16.assign(S, 0);
-    out.w16.assign(S, 0);
-    out.d8.assign(S, 0);
+    out.tgt16.assign(R, 0);
+    out.w16.assign(R, 0);
+    out.d8.assign(R, 0);
   } else {
-    out.rec8.assign(S, 0);
+    out.rec8.assign(R, 0);
   }
 
   // Pass 2: regenerate and place; per-thread worst-case input per receiver.

@@ -13,6 +13,20 @@ namespace snn {
 constexpr uint32_t kThrLds = 8192;
 constexpr uint32_t kMetaLds = 512;
 
+// LDS engine: neurons the whole grid can hold (one 512-neuron window per CU,
+// or two 256-neuron windows), thalamic table entries its LDS copies hold, and
+// sender classes (instance slot x population) one window can receive from.
+constexpr uint32_t kLdsNeurons = 131072;
+constexpr uint32_t kLdsTab = 32;
+constexpr uint32_t kWinClasses = 16;
+
+// One sender class as seen from one target window: senders [first, first + n)
+// (global ids) own `cap` record slots each in the window, the first at `base`.
+struct WinClass {
+  uint64_t base;
+  uint32_t first, n, cap, pad;
+};
+
 // Small control block in device memory.
 struct Control {
   uint64_t t_base;        // first step of the next launch
@@ -66,7 +80,11 @@ struct DeviceNet {
   Control *ctl = nullptr;
   SegEntry *seg_list = nullptr;     // persistent: [3][ntot * nwin_max]
   uint32_t lds_window = 0;          // LDS engine: neurons per block (256 or 512), else 0
-  uint32_t *flags = nullptr;        // LDS engine: per-block barrier epochs
+  const WinClass *wcls = nullptr;   // LDS engine: [windows][kWinClasses]
+  const uint2 *wrel = nullptr;      // LDS engine: per window, the blocks [x, y) that reach it
+  const uint32_t *outdeg = nullptr; // LDS engine: synapses per sender [ntot]
+  uint64_t *lflags = nullptr;       // LDS engine: [2][windows] flag words
+  uint32_t *llist = nullptr;        // LDS engine: [3][ntot] senders beyond the inline ones
 };
 
 struct LaunchShape {

@@ -845,116 +845,200 @@ hipError_t launch_persistent(const DeviceNet &d, const LaunchShape &sh, uint32_t
 // LDS engine: the destination-partitioned form of the persistent loop.
 //
 // Block b owns the WN neurons [b WN, (b+1) WN) and their 64 ring rows, kept in
-// LDS for the whole chunk; the synapses are stored per (sender, destination
-// window), so each block delivers only its own segment of every sender's row
-// -- the paper's disjoint synapse classes by destination (Sec. 3.6), one class
-// per block -- with LDS atomics instead of device-scope ones.  Blocks share
-// only the per-step sender list (16-byte entries, device-coherent loads and
-// stores) and an epoch-flag grid barrier that uses no atomics: each block
-// stores its epoch into its own flag and polls all flags.
+// LDS for the whole chunk.  Synapses are stored per (sender, destination
+// window) in fixed-capacity segments, so a block finds its segment of any
+// sender's row from the sender's id alone -- the paper's disjoint synapse
+// classes by destination (Sec. 3.6), one class per block -- and adds it into
+// its ring with LDS atomics.
 //
-// The iteration structure is the persistent kernel's: (a) completes step t-1
-// from ring row t-1, (b) decides step t and publishes its senders, (c)
-// delivers step t-1's senders into rows t .. t+62.
+// Blocks exchange nothing but their senders.  Per step each block publishes
+// one 64-bit flag word: the step's epoch, its spike count and the window
+// offsets of its first four spikes (further ones go to a list in memory).
+// The flags are also the grid barrier: a block waits until every block whose
+// neurons can reach its window (the blocks of its own instances) has
+// published the step, and then holds their senders.  No atomics are used.
+//
+// Iteration it (t = t0 + it):
+//   (a) complete step t-1 from ring row t-1;
+//   issue the record loads of step t-1's senders (staged at the end of the
+//   previous iteration);
+//   (b) decide step t and publish the flag;
+//   (c) add the records into rows t .. t+62;
+//   wait for the step-t flags of the relevant blocks and stage the senders.
+// The record loads are in flight while (b) runs.
 // ---------------------------------------------------------------------------
-constexpr uint32_t kLdsSeg = 512;
+constexpr uint32_t kInline = 4;  // senders carried in a flag word
 
-struct SenderEntry {
-  uint32_t gid;        // global id of the sender
-  uint32_t segrow;     // its first storage segment
-  uint32_t win_first;  // global index of its instance's first target window
-  uint32_t nwin;       // target windows of its instance
-};
-
-__device__ __forceinline__ void st_sender(SegEntry *e, SenderEntry v) {
-  uint64_t *p = reinterpret_cast<uint64_t *>(e);
-  st_ag(p, uint64_t(v.gid) | (uint64_t(v.segrow) << 32));
-  st_ag(p + 1, uint64_t(v.win_first) | (uint64_t(v.nwin) << 32));
+// Flag word: bits 0-15 epoch (mod 2^16), 16-25 spike count, then 9 bits per
+// inline sender (its offset in the window).
+__device__ __forceinline__ uint32_t flag_count(uint64_t f) { return uint32_t(f >> 16) & 1023u; }
+__device__ __forceinline__ uint32_t flag_local(uint64_t f, uint32_t k) {
+  return uint32_t(f >> (26 + 9 * k)) & 511u;
 }
 
-__device__ __forceinline__ SenderEntry ld_sender(const SegEntry *e) {
-  const uint64_t *p = reinterpret_cast<const uint64_t *>(e);
-  const uint64_t a = ld_ag(p), b = ld_ag(p + 1);
-  return SenderEntry{uint32_t(a), uint32_t(a >> 32), uint32_t(b), uint32_t(b >> 32)};
-}
-
-// Atomic-free grid barrier: flags[b] holds the last epoch block b reached.
-__device__ __forceinline__ bool flag_barrier(Control *ctl, uint32_t *flags, uint32_t G,
-                                             uint32_t epoch, uint32_t spin_limit,
-                                             uint32_t *s_flag) {
-  __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): this wave's stores are performed
-  __syncthreads();
-  if (threadIdx.x < 64) {
-    if (threadIdx.x == 0) st_ag(&flags[blockIdx.x], epoch);
-    uint32_t spins = 0;
-    bool ok = true;
-    for (;;) {
-      bool mine = true;
-      for (uint32_t i = __lane_id(); i < G; i += 64)
-        mine = mine && int32_t(ld_ag(&flags[i]) - epoch) >= 0;
-      if (__all(mine)) break;
-      __builtin_amdgcn_s_sleep(1);
-      if ((++spins & 63u) == 0 && (ld_ag(&ctl->error) != 0 || spins > spin_limit)) {
-        if (threadIdx.x == 0) st_ag(&ctl->error, 2u);
-        ok = false;
-        break;
+// Stages senders [j0, j0 + nb) of the current sender set (nonzero blocks in
+// s_nzf / s_nzp / s_nzb): the address of each sender's segment in this window
+// goes to s_sb, the exclusive prefix of the segment capacities to s_sx.
+// Returns the record slots of the batch.
+template <int WN, int NC>
+__device__ __forceinline__ uint32_t stage_senders(const DeviceNet &d, uint32_t j0, uint32_t nb,
+                                                  uint32_t nnz, uint32_t lslot,
+                                                  const uint64_t *s_nzf, const uint32_t *s_nzp,
+                                                  const uint16_t *s_nzb, const WinClass *s_cls,
+                                                  uint64_t *s_sb, uint32_t *s_sx,
+                                                  uint32_t *s_tmp) {
+  const uint32_t tid = threadIdx.x;
+  uint32_t cap = 0;
+  uint64_t base = 0;
+  if (tid < nb) {
+    const uint32_t j = j0 + tid;
+    uint32_t lo = 0, hi = nnz;
+    while (hi - lo > 1) {
+      const uint32_t mid = (lo + hi) >> 1;
+      if (s_nzp[mid] <= j) lo = mid; else hi = mid;
+    }
+    const uint32_t kk = j - s_nzp[lo];
+    const uint32_t src = s_nzb[lo];
+    const uint32_t loc =
+        kk < kInline ? flag_local(s_nzf[lo], kk)
+                     : ld_ag(d.llist + size_t(lslot) * d.ntot + size_t(src) * WN + kk);
+    const uint32_t gid = src * WN + loc;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      const uint32_t off = gid - s_cls[c].first;
+      if (off < s_cls[c].n) {
+        cap = s_cls[c].cap;
+        base = s_cls[c].base + uint64_t(off) * cap;
       }
     }
-    if (threadIdx.x == 0) *s_flag = ok ? 1u : 0u;
   }
+  uint32_t total;
+  const uint32_t ex = block_exclusive_scan<256>(cap, s_tmp, total);
+  s_sb[tid] = base;
+  s_sx[tid] = ex;
   __syncthreads();
-  return *s_flag != 0;
+  return total;
 }
+
+// Up to UR record slots per thread: slot e = e0 + threadIdx.x + u * 256 of the
+// staged batch.  load() issues the loads, apply() adds the records into the
+// ring rows (t_src + delay); empty slots (delay 0) are skipped.
+template <bool COMP, int UR>
+struct RecordBatch {
+  uint64_t rec[COMP ? 1 : UR];
+  uint32_t tw[COMP ? UR : 1];   // compressed: target offset | weight << 16
+  uint32_t dl[COMP ? UR : 1];
+
+  __device__ __forceinline__ void load(const DeviceNet &d, const uint64_t *s_sb,
+                                       const uint32_t *s_sx, uint32_t nb, uint32_t e0,
+                                       uint32_t total) {
+#pragma unroll
+    for (int u = 0; u < UR; ++u) {
+      const uint32_t e = e0 + threadIdx.x + uint32_t(u) * 256u;
+      uint64_t idx = 0;
+      const bool ok = e < total;
+      if (ok) {
+        uint32_t lo = 0, hi = nb;
+        while (hi - lo > 1) {
+          const uint32_t mid = (lo + hi) >> 1;
+          if (s_sx[mid] <= e) lo = mid; else hi = mid;
+        }
+        idx = s_sb[lo] + (e - s_sx[lo]);
+      }
+      if (COMP) {
+        tw[u] = ok ? uint32_t(__builtin_nontemporal_load(d.tgt16 + idx)) |
+                         (uint32_t(uint16_t(__builtin_nontemporal_load(d.w16 + idx))) << 16)
+                   : 0u;
+        dl[u] = ok ? uint32_t(__builtin_nontemporal_load(d.d8 + idx)) : 0u;
+      } else {
+        rec[u] = ok ? __builtin_nontemporal_load(d.rec8 + idx) : 0ull;
+      }
+    }
+  }
+
+  template <int WN>
+  __device__ __forceinline__ void apply(int32_t *s_ring, uint64_t t_src, uint32_t wb0) const {
+#pragma unroll
+    for (int u = 0; u < UR; ++u) {
+      uint32_t delay, loc;
+      int32_t wq;
+      if (COMP) {
+        delay = dl[u];
+        loc = tw[u] & 0xFFFFu;
+        wq = int32_t(int16_t(tw[u] >> 16)) * 8;
+      } else {
+        const uint32_t hiw = uint32_t(rec[u] >> 32);
+        delay = hiw & 63u;
+        loc = (hiw >> 6) - wb0;
+        wq = int32_t(uint32_t(rec[u]));
+      }
+      if (delay) atomicAdd(&s_ring[((t_src + delay) & (kRing - 1)) * WN + loc], wq);
+    }
+  }
+};
 
 template <int WN, bool COMP>
 __global__ __launch_bounds__(256) void k_lds(DeviceNet d, uint32_t n_steps, uint32_t spin_limit) {
   constexpr uint32_t BS = 256;
-  constexpr uint32_t NQ = WN / 4;          // quads of the window (one per thread)
-  constexpr uint32_t IPT = kLdsSeg / BS;
-  constexpr uint32_t TSTRIDE = kMaxPoisson + 8;
+  constexpr uint32_t NQ = WN / 4;             // quads of the window (one per thread)
+  constexpr int NSLOT = WN / 256;             // instances a window can overlap
+  constexpr int NC = 8 * NSLOT;               // sender classes that can reach it
+  constexpr uint32_t TS = kLdsTab + 8;        // stride of an LDS thalamic table
+  constexpr uint32_t NZ = kLdsNeurons / WN;   // largest grid of this window size
+  constexpr int NJ = NZ / 64;                 // flags per lane of the polling wave
+  constexpr uint32_t RC = WN + 128;           // raster staging entries
+  constexpr int UR = 8;                       // record loads in flight per thread
   __shared__ int32_t s_ring[kRing * WN];
-  __shared__ uint32_t s_thr[2 * 8 * TSTRIDE];
-  __shared__ uint2 s_meta[16];
-  __shared__ SegStage s_seg[kLdsSeg];
-  __shared__ uint32_t s_excl[kLdsSeg];
-  __shared__ uint32_t s_tmp[BS / 64], s_wave[BS / 64];
-  __shared__ uint32_t s_base, s_flag, s_n, s_inst[2];
+  __shared__ uint32_t s_thr[NSLOT * 8 * TS];
+  __shared__ uint2 s_meta[NSLOT * 8];
+  __shared__ WinClass s_cls[NC];
+  __shared__ uint64_t s_nzf[NZ];
+  __shared__ uint32_t s_nzp[NZ];
+  __shared__ uint16_t s_nzb[NZ];
+  __shared__ uint64_t s_sb[BS];
+  __shared__ uint32_t s_sx[BS];
+  __shared__ uint64_t s_rast[RC];
+  __shared__ uint32_t s_tmp[BS / 64], s_wave[BS / 64], s_inl[kInline];
+  __shared__ uint32_t s_inst[NSLOT], s_flag, s_n, s_nnz, s_cnt;
   __shared__ unsigned long long s_rbase;
 
-  const uint32_t G = gridDim.x;
+  const uint32_t G = gridDim.x, blk = blockIdx.x;
   const uint32_t tid = threadIdx.x, wave = tid >> 6, lane = __lane_id();
-  const uint32_t wb0 = blockIdx.x * WN;
+  const uint32_t wb0 = blk * WN;
   const uint32_t q = wb0 / 4 + tid;
   const bool owner = tid < NQ && q < d.nquads;
   const uint64_t t0 = d.ctl->t_base;
   const uint32_t ep0 = d.ctl->epoch;
   const Props k{d.consts->p11, d.consts->p22, d.consts->p21};
-  const size_t lstride = size_t(d.ntot);
+  const uint2 rel = d.wrel[blk];   // blocks whose senders can reach this window
+  uint64_t *const flags = d.lflags;
 
   // Ring rows of the window into LDS.
   for (uint32_t i = tid; i < kRing * WN; i += BS) {
     const uint32_t r = i / WN, c = i % WN;
     s_ring[i] = wb0 + c < d.ntot ? d.W[size_t(r) * d.ntot + wb0 + c] : 0;
   }
-  // Thalamic tables of the (at most two, 256-aligned) instances in the window.
-  if (tid < 2) {
+  if (tid < uint32_t(NC)) s_cls[tid] = d.wcls[size_t(blk) * kWinClasses + tid];
+  // Thalamic tables of the (256-aligned) instances in the window.
+  if (tid < uint32_t(NSLOT)) {
     const uint32_t qq = wb0 / 4 + tid * 64;
     s_inst[tid] = qq < d.nquads ? d.qinfo[qq] >> 24 : 0xFFFFFFFFu;
   }
   __syncthreads();
-  if (tid < 16) {
+  if (tid < uint32_t(NSLOT * 8)) {
     const uint32_t slot = tid >> 3, p = tid & 7u;
     const uint32_t inst = s_inst[slot];
     uint2 m = make_uint2(0, 0);
     if (inst != 0xFFFFFFFFu) m = d.pmeta[inst * 8 + p];
-    const uint32_t off = (slot * 8 + p) * TSTRIDE;
-    for (uint32_t kk = 0; kk < TSTRIDE; ++kk)
+    const uint32_t off = (slot * 8 + p) * TS;
+    for (uint32_t kk = 0; kk < TS; ++kk)
       s_thr[off + kk] = kk < m.y ? d.thr[m.x + kk] : 0xFFFFFFFFu;
     s_meta[slot * 8 + p] = make_uint2(off, m.y);
   }
 
   float U[4] = {0, 0, 0, 0}, I[4] = {0, 0, 0, 0};
   uint32_t R = 0, Tp = 0, QI = 0, PC = 0, slot = 0, c_spk = 0, c_poi = 0;
+  uint32_t OD[4] = {0, 0, 0, 0};
   int64_t c_con = 0;
   uint64_t c_ev = 0, seed = 0;
   int32_t wext = 0;
@@ -969,28 +1053,39 @@ __global__ __launch_bounds__(256) void k_lds(DeviceNet d, uint32_t n_steps, uint
     PC = quad_code(ip, QI & 0xFFFFFFu);
     seed = ip->seed;
     wext = ip->w_ext_q;
+    const uint4 od = *reinterpret_cast<const uint4 *>(d.outdeg + 4 * size_t(q));
+    OD[0] = od.x; OD[1] = od.y; OD[2] = od.z; OD[3] = od.w;
   }
   __syncthreads();
-  if (owner) slot = (QI >> 24) == s_inst[0] ? 0u : 1u;
+  if (owner) slot = NSLOT > 1 && (QI >> 24) != s_inst[0] ? 1u : 0u;
 
+  // Flushes the staged raster entries to the device raster.
+  uint32_t rn = 0;
+  auto flush = [&]() {
+    if (tid == 0)
+      s_rbase = atomicAdd(reinterpret_cast<unsigned long long *>(&d.ctl->raster_n),
+                          (unsigned long long)rn);
+    __syncthreads();
+    for (uint32_t i = tid; i < rn; i += BS) {
+      const uint64_t pos = s_rbase + i;
+      if (pos < d.raster_cap)
+        d.raster[pos] = s_rast[i];
+      else
+        d.ctl->overflow = 1;
+    }
+    __syncthreads();
+    rn = 0;
+  };
+
+  uint32_t n_prev = 0, nnz = 0, tot0 = 0;
   for (uint32_t it = 0; it <= n_steps; ++it) {
     const uint64_t t = t0 + it;
-    const bool has_prev = it > 0;
     const bool decide = it < n_steps;
-    SegEntry *lcur = d.seg_list + size_t(it % 3) * lstride;
-    const SegEntry *lprev = d.seg_list + size_t((it + 2) % 3) * lstride;
+    const uint32_t ep = ep0 + it + 1;         // epoch of step t's publication
+    const uint32_t lslot_prev = (ep - 1) % 3; // list of step t-1's senders
 
-    // (c) part 1: count of step t-1's senders and the first kSpec of them.
-    uint32_t nprev = 0;
-    SenderEntry spec{0, 0, 0, 0};
-    if (has_prev && wave == 0) {
-      nprev = ld_ag(&d.ctl->lcnt[(it + 2) % 3]);
-      spec = ld_sender(lprev + lane);
-    }
-    if (decide && blockIdx.x == 0 && tid == 0) st_ag(&d.ctl->lcnt[(it + 1) % 3], 0u);
-
-    // (a) complete step t-1 from ring row t-1 (LDS).
-    if (has_prev && owner) {
+    // (a) complete step t-1 from ring row t-1.
+    if (it > 0 && owner) {
       int32_t *row = s_ring + ((t - 1) & (kRing - 1)) * WN + 4 * tid;
 #pragma unroll
       for (int m = 0; m < 4; ++m) {
@@ -1003,14 +1098,19 @@ __global__ __launch_bounds__(256) void k_lds(DeviceNet d, uint32_t n_steps, uint
       }
     }
 
-    // (b) decide step t and publish the senders.
+    // Record loads of step t-1's senders (batch 0, staged at the end of the
+    // previous iteration); they stay in flight during (b).
+    RecordBatch<COMP, UR> rb;
+    if (n_prev) rb.load(d, s_sb, s_sx, min(n_prev, BS), 0, tot0);
+
+    // (b) decide step t and publish its senders.
     if (decide) {
-      uint32_t flags = 0;
+      uint32_t fl = 0;
       if (owner)
-        flags = decide_quad(s_thr, s_meta, slot * 8u, seed, QI & 0xFFFFFFu, PC, t, k, U, I, R, Tp,
-                            c_poi);
+        fl = decide_quad(s_thr, s_meta, slot * 8u, seed, QI & 0xFFFFFFu, PC, t, k, U, I, R, Tp,
+                         c_poi);
       uint32_t lo, tot;
-      wave_compact(flags, lo, tot);
+      wave_compact(fl, lo, tot);
       if (lane == 0) s_wave[wave] = tot;
       __syncthreads();
       if (tid == 0) {
@@ -1020,119 +1120,137 @@ __global__ __launch_bounds__(256) void k_lds(DeviceNet d, uint32_t n_steps, uint
           s_wave[w] = run;
           run += c;
         }
-        if (run) {
-          s_base = atomicAdd(&d.ctl->lcnt[it % 3], run);
-          s_rbase = atomicAdd(reinterpret_cast<unsigned long long *>(&d.ctl->raster_n),
-                              (unsigned long long)run);
-        }
+        s_cnt = run;
       }
       __syncthreads();
-      if (flags) {
-        const InstDev *ip = d.inst + (QI >> 24);
-        const uint32_t lq = QI & 0xFFFFFFu;
-        uint32_t o = s_wave[wave] + lo;
-        c_spk += __popc(flags);
+      const uint32_t cnt = s_cnt;
+      if (fl) {
+        uint32_t p = s_wave[wave] + lo;
+        uint32_t *lst = d.llist + size_t(ep % 3) * d.ntot + wb0;
+        c_spk += __popc(fl);
+#pragma unroll
         for (int m = 0; m < 4; ++m) {
-          if (!((flags >> m) & 1u)) continue;
-          const uint32_t gid = 4 * q + uint32_t(m);
-          const uint32_t segrow = ip->seg_base + (lq * 4u + uint32_t(m)) * ip->nwin;
-          st_sender(lcur + s_base + o, SenderEntry{gid, segrow, ip->win_first, ip->nwin});
-          c_ev += d.seg_ptr[segrow + ip->nwin] - d.seg_ptr[segrow];
-          const uint64_t pos = s_rbase + o;
-          if (pos < d.raster_cap)
-            d.raster[pos] = (t << 32) | gid;
+          if (!((fl >> m) & 1u)) continue;
+          const uint32_t loc = 4 * tid + uint32_t(m);
+          if (p < kInline)
+            s_inl[p] = loc;
           else
-            d.ctl->overflow = 1;
-          ++o;
+            st_ag(lst + p, loc);
+          s_rast[rn + p] = (t << 32) | (wb0 + loc);
+          c_ev += OD[m];
+          ++p;
         }
       }
-    }
-
-    // (c) part 2: this block's segment of every sender of step t-1.
-    if (has_prev) {
-      if (tid == 0) s_n = nprev;
+      // List entries must be performed before the flag that announces them.
+      if (cnt > kInline) __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
       __syncthreads();
-      const uint32_t n = s_n;
-      for (uint32_t b0 = 0; b0 < n; b0 += kLdsSeg) {
-        const uint32_t nb = min(kLdsSeg, n - b0);
-        uint32_t len[IPT];
-#pragma unroll
-        for (uint32_t m = 0; m < IPT; ++m) {
-          const uint32_t s2 = m * BS + tid;
-          len[m] = 0;
-          if (s2 < nb) {
-            const SenderEntry e = (b0 == 0 && s2 < kSpec) ? spec : ld_sender(lprev + b0 + s2);
-            const uint32_t w = blockIdx.x - e.win_first;
-            uint64_t st = 0;
-            if (w < e.nwin) {
-              st = d.seg_ptr[e.segrow + w];
-              len[m] = uint32_t(d.seg_ptr[e.segrow + w + 1] - st);
-            }
-            s_seg[s2].start = st;
-            s_seg[s2].len = len[m];
-          }
-        }
-        // exclusive scan in s2 order: thread tid holds s2 = tid and tid + BS
-        uint32_t total0;
-        const uint32_t run0 = block_exclusive_scan<BS>(len[0], s_tmp, total0);
-        uint32_t total1;
-        const uint32_t run1 = block_exclusive_scan<BS>(IPT > 1 ? len[IPT - 1] : 0u, s_tmp, total1);
-        if (tid < nb) s_excl[tid] = run0;
-        if (IPT > 1 && BS + tid < nb) s_excl[BS + tid] = total0 + run1;
-        const uint32_t total = total0 + (IPT > 1 ? total1 : 0u);
-        __syncthreads();
-        constexpr int U8 = 8;
-        for (uint32_t e0 = tid; e0 < total; e0 += BS * U8) {
-          uint64_t idx[U8];
-#pragma unroll
-          for (int u = 0; u < U8; ++u) {
-            const uint32_t e = e0 + uint32_t(u) * BS;
-            idx[u] = ~0ull;
-            if (e < total) {
-              uint32_t lo2 = 0, hi2 = nb;
-              while (hi2 - lo2 > 1) {
-                const uint32_t mid = (lo2 + hi2) >> 1;
-                if (s_excl[mid] <= e) lo2 = mid; else hi2 = mid;
-              }
-              idx[u] = s_seg[lo2].start + (e - s_excl[lo2]);
-            }
-          }
-          uint32_t loc[U8], dl[U8];
-          int32_t wq[U8];
-#pragma unroll
-          for (int u = 0; u < U8; ++u) {
-            loc[u] = 0;
-            dl[u] = 0;
-            wq[u] = 0;
-            if (idx[u] != ~0ull) {
-              if (COMP) {
-                loc[u] = d.tgt16[idx[u]];
-                wq[u] = int32_t(d.w16[idx[u]]) * 8;
-                dl[u] = d.d8[idx[u]];
-              } else {
-                const uint64_t rec = d.rec8[idx[u]];
-                const uint32_t hiw = uint32_t(rec >> 32);
-                wq[u] = int32_t(uint32_t(rec));
-                loc[u] = (hiw >> 6) - wb0;
-                dl[u] = hiw & 63u;
-              }
-            }
-          }
-#pragma unroll
-          for (int u = 0; u < U8; ++u)
-            if (idx[u] != ~0ull)
-              atomicAdd(&s_ring[((t - 1 + dl[u]) & (kRing - 1)) * WN + loc[u]], wq[u]);
-        }
-        __syncthreads();
+      if (tid == 0) {
+        uint64_t f = uint64_t(ep & 0xFFFFu) | (uint64_t(cnt) << 16);
+        for (uint32_t kk = 0; kk < kInline && kk < cnt; ++kk)
+          f |= uint64_t(s_inl[kk]) << (26 + 9 * kk);
+        st_ag(flags + size_t(ep & 1u) * G + blk, f);
       }
+      rn += cnt;
+      if (rn > RC - WN) flush();
     }
 
-    if (it == n_steps) break;
-    if (!flag_barrier(d.ctl, d.flags, G, ep0 + it + 1, spin_limit, &s_flag)) break;
+    // (c) step t-1's senders into rows t .. t+62.
+    if (n_prev) {
+      const uint64_t tsrc = t - 1;
+      rb.template apply<WN>(s_ring, tsrc, wb0);
+      const uint32_t nb0 = min(n_prev, BS);
+      for (uint32_t e0 = BS * UR; e0 < tot0; e0 += BS * UR) {
+        RecordBatch<COMP, UR> r2;
+        r2.load(d, s_sb, s_sx, nb0, e0, tot0);
+        r2.template apply<WN>(s_ring, tsrc, wb0);
+      }
+      for (uint32_t j0 = BS; j0 < n_prev; j0 += BS) {
+        __syncthreads();
+        const uint32_t nb = min(BS, n_prev - j0);
+        const uint32_t tot = stage_senders<WN, NC>(d, j0, nb, nnz, lslot_prev, s_nzf, s_nzp, s_nzb,
+                                                   s_cls, s_sb, s_sx, s_tmp);
+        for (uint32_t e0 = 0; e0 < tot; e0 += BS * UR) {
+          RecordBatch<COMP, UR> r2;
+          r2.load(d, s_sb, s_sx, nb, e0, tot);
+          r2.template apply<WN>(s_ring, tsrc, wb0);
+        }
+      }
+    }
+    if (!decide) break;
+
+    // Wait for step t's flags of the relevant blocks; collect their senders.
+    __syncthreads();
+    if (wave == 0) {
+      uint64_t fv[NJ];
+      const uint64_t *fs = flags + size_t(ep & 1u) * G;
+      uint32_t spins = 0;
+      bool ok = true;
+      for (;;) {
+        bool mine = true;
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) {
+          const uint32_t bb = rel.x + lane + 64u * uint32_t(j);
+          fv[j] = 0;
+          if (bb < rel.y) {
+            fv[j] = ld_ag(fs + bb);
+            mine = mine && (uint32_t(fv[j]) & 0xFFFFu) == (ep & 0xFFFFu);
+          }
+        }
+        if (__all(mine)) break;
+        __builtin_amdgcn_s_sleep(1);
+        if ((++spins & 63u) == 0 && (ld_ag(&d.ctl->error) != 0 || spins > spin_limit)) {
+          if (lane == 0) st_ag(&d.ctl->error, 2u);
+          ok = false;
+          break;
+        }
+      }
+      uint32_t nzc = 0, sc = 0;
+#pragma unroll
+      for (int j = 0; j < NJ; ++j) {
+        const uint32_t c = flag_count(fv[j]);
+        nzc += c ? 1u : 0u;
+        sc += c;
+      }
+      // inclusive wave scan of (senders << 10 | nonzero blocks)
+      const uint32_t v = (sc << 10) | nzc;
+      uint32_t x = v;
+#pragma unroll
+      for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(x, o);
+        if (lane >= uint32_t(o)) x += y;
+      }
+      const uint32_t all = __shfl(x, 63);
+      uint32_t pz = (x - v) & 1023u, ps = (x - v) >> 10;
+#pragma unroll
+      for (int j = 0; j < NJ; ++j) {
+        const uint32_t c = flag_count(fv[j]);
+        if (c) {
+          s_nzf[pz] = fv[j];
+          s_nzp[pz] = ps;
+          s_nzb[pz] = uint16_t(rel.x + lane + 64u * uint32_t(j));
+          ++pz;
+          ps += c;
+        }
+      }
+      if (lane == 0) {
+        s_nnz = all & 1023u;
+        s_n = all >> 10;
+        s_flag = ok ? 1u : 0u;
+      }
+    }
+    __syncthreads();
+    if (!s_flag) break;
+    n_prev = s_n;
+    nnz = s_nnz;
+    tot0 = 0;
+    if (n_prev)
+      tot0 = stage_senders<WN, NC>(d, 0, min(n_prev, BS), nnz, ep % 3, s_nzf, s_nzp, s_nzb, s_cls,
+                                   s_sb, s_sx, s_tmp);
   }
 
-  // Ring rows, state and counters back to memory.
+  // Raster, ring rows, state and counters back to memory.
   __syncthreads();
+  if (rn) flush();
   for (uint32_t i = tid; i < kRing * WN; i += BS) {
     const uint32_t r = i / WN, c = i % WN;
     if (wb0 + c < d.ntot) d.W[size_t(r) * d.ntot + wb0 + c] = s_ring[i];
@@ -1166,9 +1284,6 @@ __global__ __launch_bounds__(256) void k_lds(DeviceNet d, uint32_t n_steps, uint
     const uint64_t done =
         __hip_atomic_fetch_add(&d.ctl->exit_count, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (done == G - 1) {
-      st_ag(&d.ctl->lcnt[0], 0u);
-      st_ag(&d.ctl->lcnt[1], 0u);
-      st_ag(&d.ctl->lcnt[2], 0u);
       st_ag(&d.ctl->exit_count, 0ull);
       st_ag(&d.ctl->epoch, ep0 + n_steps);
       st_ag(&d.ctl->t_base, t0 + n_steps);
@@ -1193,13 +1308,14 @@ int lds_max_grid(uint32_t window) {
     return 0;
   hipDeviceProp_t prop;
   if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return 0;
-  return per_cu * prop.multiProcessorCount;
+  return std::min<int>(per_cu * prop.multiProcessorCount, int(kLdsNeurons / window));
 }
 
 hipError_t launch_lds(const DeviceNet &d, uint32_t n, hipStream_t s) {
   LdsFn fn = lds_fn(d.lds_window, d.syn_format == SNN_SYN_COMPRESSED5);
   if (!fn) return hipErrorInvalidConfiguration;
   const uint32_t grid = (d.ntot + d.lds_window - 1) / d.lds_window;
+  if (grid > kLdsNeurons / d.lds_window) return hipErrorInvalidConfiguration;
   DeviceNet dv = d;
   uint32_t steps = n;
   uint32_t spin = 1u << 24;

@@ -288,10 +288,17 @@ int snn_build(const snn_config *cfg, snn_net **out) {
   h->engine = cfg->engine == SNN_ENGINE_AUTO ? SNN_ENGINE_LDS : cfg->engine;
   uint32_t lds_window = 0;
   if (h->engine == SNN_ENGINE_LDS) {
-    lds_window = choose_lds_window(ntot, cfg->block_size, cfg->grid_blocks);
+    uint32_t tab = 0;
+    for (uint32_t k = 0; k < ni; ++k) tab = std::max(tab, thalamic_table_max(cfg->inst[k]));
+    lds_window = tab <= kLdsTab ? choose_lds_window(ntot, cfg->block_size, cfg->grid_blocks) : 0;
     if (!lds_window) {
       if (cfg->engine == SNN_ENGINE_LDS) {
-        fail(h, SNN_E_RANGE, "the LDS engine holds at most %u neurons on this device", lds_capacity());
+        if (tab > kLdsTab)
+          fail(h, SNN_E_RANGE, "the LDS engine holds thalamic tables of at most %u entries (need %u)",
+               kLdsTab, tab);
+        else
+          fail(h, SNN_E_RANGE, "the LDS engine holds at most %u neurons on this device",
+               lds_capacity());
         return bail(SNN_E_RANGE);
       }
       h->engine = SNN_ENGINE_PERSISTENT;
@@ -301,7 +308,7 @@ int snn_build(const snn_config *cfg, snn_net **out) {
   // ---- sample every instance on the host ----
   std::vector<HostInstance> hi(ni);
   uint32_t nwin_max = 1;
-  uint64_t nseg_tot = 0, nsyn_tot = 0, nthr = 0;
+  uint64_t nseg_tot = 0, nrec_tot = 0, nthr = 0;
   for (uint32_t k = 0; k < ni; ++k) {
     InstMeta &m = h->im[k];
     uint32_t wsize = kNoWindows, worigin = 0;
@@ -312,8 +319,8 @@ int snn_build(const snn_config *cfg, snn_net **out) {
       wsize = 1u << kTargetBlockBits;
     }
     std::string e;
-    int rc = sample_instance(cfg->inst[k], cfg->syn_format, wsize, worigin, cfg->host_threads,
-                             hi[k], e);
+    int rc = sample_instance(cfg->inst[k], cfg->syn_format, wsize, worigin, lds_window != 0,
+                             cfg->host_threads, hi[k], e);
     if (rc) {
       fail(h, rc, "instance %u: %s", k, e.c_str());
       return bail(rc);
@@ -323,8 +330,8 @@ int snn_build(const snn_config *cfg, snn_net **out) {
     m.w_f = hi[k].w_f;
     m.w_ext_q = hi[k].w_ext_q;
     nwin_max = std::max(nwin_max, hi[k].nwin);
-    nseg_tot += uint64_t(m.n) * hi[k].nwin;
-    nsyn_tot += m.nsyn;
+    if (!hi[k].padded) nseg_tot += uint64_t(m.n) * hi[k].nwin;
+    nrec_tot += hi[k].nrec;
     for (int p = 0; p < 8; ++p) nthr += hi[k].thr_len[p];
     h->n_real += m.n;
   }
@@ -376,11 +383,11 @@ int snn_build(const snn_config *cfg, snn_net **out) {
   ALLOC(d.W, size_t(kRing) * d.ntot);
   ALLOC(d_seg, nseg_tot + 1);
   if (comp) {
-    ALLOC(d_tgt16, std::max<uint64_t>(1, nsyn_tot));
-    ALLOC(d_w16, std::max<uint64_t>(1, nsyn_tot));
-    ALLOC(d_d8, std::max<uint64_t>(1, nsyn_tot));
+    ALLOC(d_tgt16, std::max<uint64_t>(1, nrec_tot));
+    ALLOC(d_w16, std::max<uint64_t>(1, nrec_tot));
+    ALLOC(d_d8, std::max<uint64_t>(1, nrec_tot));
   } else {
-    ALLOC(d_rec8, std::max<uint64_t>(1, nsyn_tot));
+    ALLOC(d_rec8, std::max<uint64_t>(1, nrec_tot));
   }
   ALLOC(d.spk_list, 2 * size_t(d.ntot));
   ALLOC(d.raster, cap);
@@ -388,9 +395,18 @@ int snn_build(const snn_config *cfg, snn_net **out) {
   ALLOC(d.events, ni);
   ALLOC(d.consts, 1);
   ALLOC(d.ctl, 1);
-  const bool want_persistent = h->engine != SNN_ENGINE_STEPWISE;
-  if (want_persistent) ALLOC(d.seg_list, 3 * size_t(d.ntot) * nwin_max);
-  if (lds_window) ALLOC(d.flags, (d.ntot + lds_window - 1) / lds_window);
+  if (h->engine == SNN_ENGINE_PERSISTENT) ALLOC(d.seg_list, 3 * size_t(d.ntot) * nwin_max);
+  const uint32_t nwin_lds = lds_window ? (d.ntot + lds_window - 1) / lds_window : 0;
+  WinClass *d_wcls = nullptr;
+  uint2 *d_wrel = nullptr;
+  uint32_t *d_outdeg = nullptr;
+  if (lds_window) {
+    ALLOC(d_wcls, size_t(nwin_lds) * kWinClasses);
+    ALLOC(d_wrel, nwin_lds);
+    ALLOC(d_outdeg, d.ntot);
+    ALLOC(d.lflags, 2 * size_t(nwin_lds));
+    ALLOC(d.llist, 3 * size_t(d.ntot));
+  }
 #undef ALLOC
 
   // ---- host staging and upload ----
@@ -427,7 +443,7 @@ int snn_build(const snn_config *cfg, snn_net **out) {
     for (uint32_t lq = 0; lq < m.npad / 4; ++lq) qinfo[m.gbase / 4 + lq] = (k << 24) | lq;
     std::copy(x.u0.begin(), x.u0.end(), u0.begin() + m.gbase);
     for (uint64_t s = 0; s + 1 < x.seg_ptr.size(); ++s) seg.push_back(syn_base + x.seg_ptr[s]);
-    syn_base += x.nsyn;
+    syn_base += x.nrec;
   }
   seg.push_back(syn_base);
   thr.resize(thr.size() + 8, 0xFFFFFFFFu);  // padding read by the 8-wide table scan
@@ -451,21 +467,59 @@ int snn_build(const snn_config *cfg, snn_net **out) {
   UPLOAD(d_pmeta, pmeta.data(), pmeta.size() * sizeof(uint2));
   UPLOAD(d.U, u0.data(), u0.size() * sizeof(float));
   UPLOAD(d_seg, seg.data(), seg.size() * sizeof(uint64_t));
+  if (lds_window) {
+    // Per target window: the sender classes of the (at most two) instances it
+    // overlaps, and the block range of those instances.
+    std::vector<WinClass> wcls(size_t(nwin_lds) * kWinClasses);
+    std::vector<uint2> wrel(nwin_lds, make_uint2(0xFFFFFFFFu, 0u));
+    std::vector<uint32_t> used(nwin_lds, 0), outdeg(d.ntot, 0);
+    const uint32_t slots = lds_window / kInstAlign;
+    uint64_t rb = 0;
+    for (uint32_t k = 0; k < ni; ++k) {
+      const HostInstance &x = hi[k];
+      const InstMeta &m = h->im[k];
+      for (uint32_t w = 0; w < x.nwin; ++w) {
+        const uint32_t gw = x.win_first + w;
+        if (gw >= nwin_lds || used[gw] >= slots) {
+          fail(h, SNN_E_RANGE, "window %u overlaps more than %u instances", gw, slots);
+          return bail(SNN_E_RANGE);
+        }
+        const uint32_t sl = used[gw]++;
+        for (int c = 0; c < 8; ++c) {
+          WinClass &e = wcls[size_t(gw) * kWinClasses + sl * 8 + c];
+          e.base = rb + x.cls_base[size_t(w) * 8 + c];
+          e.first = m.gbase + x.pop_off[c];
+          e.n = x.pop_off[c + 1] - x.pop_off[c];
+          e.cap = x.cls_cap[size_t(w) * 8 + c];
+        }
+      }
+      for (uint32_t w = 0; w < x.nwin; ++w) {
+        uint2 &r = wrel[x.win_first + w];
+        r.x = std::min(r.x, x.win_first);
+        r.y = std::max(r.y, x.win_first + x.nwin);
+      }
+      std::copy(x.outdeg.begin(), x.outdeg.end(), outdeg.begin() + m.gbase);
+      rb += x.nrec;
+    }
+    UPLOAD(d_wcls, wcls.data(), wcls.size() * sizeof(WinClass));
+    UPLOAD(d_wrel, wrel.data(), wrel.size() * sizeof(uint2));
+    UPLOAD(d_outdeg, outdeg.data(), outdeg.size() * sizeof(uint32_t));
+  }
   syn_base = 0;
   for (uint32_t k = 0; k < ni; ++k) {
     HostInstance &x = hi[k];
     if (comp) {
-      UPLOAD(d_tgt16 + syn_base, x.tgt16.data(), x.nsyn * sizeof(uint16_t));
-      UPLOAD(d_w16 + syn_base, x.w16.data(), x.nsyn * sizeof(int16_t));
-      UPLOAD(d_d8 + syn_base, x.d8.data(), x.nsyn * sizeof(uint8_t));
+      UPLOAD(d_tgt16 + syn_base, x.tgt16.data(), x.nrec * sizeof(uint16_t));
+      UPLOAD(d_w16 + syn_base, x.w16.data(), x.nrec * sizeof(int16_t));
+      UPLOAD(d_d8 + syn_base, x.d8.data(), x.nrec * sizeof(uint8_t));
     } else {
       if (h->im[k].gbase) {  // targets become global ids
         const uint64_t add = uint64_t(h->im[k].gbase) << 38;
         for (auto &r : x.rec8) r += add;
       }
-      UPLOAD(d_rec8 + syn_base, x.rec8.data(), x.nsyn * sizeof(uint64_t));
+      UPLOAD(d_rec8 + syn_base, x.rec8.data(), x.nrec * sizeof(uint64_t));
     }
-    syn_base += x.nsyn;
+    syn_base += x.nrec;
     x = HostInstance();  // release host copies early
   }
 #undef UPLOAD
@@ -480,6 +534,9 @@ int snn_build(const snn_config *cfg, snn_net **out) {
   d.tgt16 = d_tgt16;
   d.w16 = d_w16;
   d.d8 = d_d8;
+  d.wcls = d_wcls;
+  d.wrel = d_wrel;
+  d.outdeg = d_outdeg;
   if (hipMemset(d.I, 0, d.ntot * sizeof(float)) != hipSuccess ||
       hipMemset(d.R4, 0, d.nquads * sizeof(uint32_t)) != hipSuccess ||
       hipMemset(d.W, 0, size_t(kRing) * d.ntot * sizeof(int32_t)) != hipSuccess ||
@@ -487,7 +544,7 @@ int snn_build(const snn_config *cfg, snn_net **out) {
       hipMemset(d.wave_ctr, 0, 4 * size_t(d.nquads / 64) * sizeof(int64_t)) != hipSuccess ||
       hipMemset(d.events, 0, ni * sizeof(uint64_t)) != hipSuccess ||
       hipMemset(d.ctl, 0, sizeof(Control)) != hipSuccess ||
-      (d.flags && hipMemset(d.flags, 0, ((d.ntot + lds_window - 1) / lds_window) * sizeof(uint32_t)) != hipSuccess)) {
+      (d.lflags && hipMemset(d.lflags, 0, 2 * size_t(nwin_lds) * sizeof(uint64_t)) != hipSuccess)) {
     fail(h, SNN_E_HIP, "device memset failed");
     return bail(SNN_E_HIP);
   }
@@ -678,12 +735,20 @@ int snn_time_steps(snn_net *h, uint64_t n_steps, double *elapsed_ms) {
 
 int snn_sample_network(const snn_instance_cfg *inst, uint32_t syn_format, int32_t host_threads,
                        snn_host_network **out) {
+  return snn_sample_network_windows(inst, syn_format, 0, host_threads, out);
+}
+
+int snn_sample_network_windows(const snn_instance_cfg *inst, uint32_t syn_format, uint32_t window,
+                               int32_t host_threads, snn_host_network **out) {
   if (!inst || !out) return fail(nullptr, SNN_E_INVAL, "NULL argument");
   *out = nullptr;
+  if (window != 0 && window != 256 && window != 512)
+    return fail(nullptr, SNN_E_INVAL, "window must be 0, 256 or 512");
   HostInstance x;
   std::string e;
-  const uint32_t wsize = syn_format == SNN_SYN_COMPRESSED5 ? (1u << kTargetBlockBits) : kNoWindows;
-  int rc = sample_instance(*inst, syn_format, wsize, 0, host_threads, x, e);
+  uint32_t wsize = syn_format == SNN_SYN_COMPRESSED5 ? (1u << kTargetBlockBits) : kNoWindows;
+  if (window) wsize = window;
+  int rc = sample_instance(*inst, syn_format, wsize, 0, window != 0, host_threads, x, e);
   if (rc) return fail(nullptr, rc, "%s", e.c_str());
   snn_host_network *n = static_cast<snn_host_network *>(std::calloc(1, sizeof(snn_host_network)));
   if (!n) return fail(nullptr, SNN_E_NOMEM, "host allocation failed");
@@ -699,25 +764,56 @@ int snn_sample_network(const snn_instance_cfg *inst, uint32_t syn_format, int32_
     snn_free_network(n);
     return fail(nullptr, SNN_E_NOMEM, "host allocation failed");
   }
-  for (uint32_t i = 0; i <= x.n; ++i) n->row_ptr[i] = x.seg_ptr[uint64_t(i) * x.nwin];
   std::memcpy(n->u0, x.u0.data(), x.n * sizeof(float));
   const bool comp = syn_format == SNN_SYN_COMPRESSED5;
-  for (uint32_t i = 0; i < x.n; ++i)
+  // Decode rows in storage order: by target window, then segment order.
+  uint64_t o = 0;
+  for (uint32_t i = 0; i < x.n; ++i) {
+    n->row_ptr[i] = o;
+    uint32_t c = 0;
+    while (x.padded && i >= x.pop_off[c + 1]) ++c;
     for (uint32_t w = 0; w < x.nwin; ++w) {
       const uint64_t s = uint64_t(i) * x.nwin + w;
-      for (uint64_t e2 = x.seg_ptr[s]; e2 < x.seg_ptr[s + 1]; ++e2) {
+      uint64_t lo = 0, hi = 0;
+      if (x.padded) {
+        const uint32_t cap = x.cls_cap[size_t(w) * 8 + c];
+        lo = x.cls_base[size_t(w) * 8 + c] + uint64_t(i - x.pop_off[c]) * cap;
+        hi = lo + cap;
+      } else {
+        lo = x.seg_ptr[s];
+        hi = x.seg_ptr[s + 1];
+      }
+      for (uint64_t e2 = lo; e2 < hi; ++e2) {
+        uint32_t post, dl;
+        int32_t wq;
         if (comp) {
-          n->post[e2] = (x.win_first + w) * x.win_size + x.tgt16[e2] - x.win_origin;
-          n->delay[e2] = x.d8[e2];
-          n->w_q[e2] = int32_t(x.w16[e2]) * 8;
+          post = (x.win_first + w) * x.win_size + x.tgt16[e2] - x.win_origin;
+          dl = x.d8[e2];
+          wq = int32_t(x.w16[e2]) * 8;
         } else {
           const uint32_t hiw = uint32_t(x.rec8[e2] >> 32);
-          n->post[e2] = hiw >> 6;
-          n->delay[e2] = uint8_t(hiw & 63u);
-          n->w_q[e2] = int32_t(uint32_t(x.rec8[e2]));
+          post = hiw >> 6;
+          dl = hiw & 63u;
+          wq = int32_t(uint32_t(x.rec8[e2]));
         }
+        if (dl == 0) continue;  // an unused slot of a padded segment
+        if (o >= x.nsyn) {
+          snn_free_network(n);
+          return fail(nullptr, SNN_E_RANGE, "storage holds more synapses than sampled");
+        }
+        n->post[o] = post;
+        n->delay[o] = uint8_t(dl);
+        n->w_q[o] = wq;
+        ++o;
       }
     }
+  }
+  n->row_ptr[x.n] = o;
+  if (o != x.nsyn) {
+    snn_free_network(n);
+    return fail(nullptr, SNN_E_RANGE, "storage holds %llu of %llu synapses",
+                (unsigned long long)o, (unsigned long long)x.nsyn);
+  }
   *out = n;
   return SNN_OK;
 }

@@ -105,7 +105,16 @@ struct HostInstance {
   // win_origin + local id; [n * nwin + 1] pointers into the record streams.
   uint32_t win_size = 0, win_origin = 0, win_first = 0;
   uint32_t nwin = 1;
-  std::vector<uint64_t> seg_ptr;
+  std::vector<uint64_t> seg_ptr;     // compact layout: segment pointers
+  // Padded layout: segment (sender s of population c, window w) holds
+  // cls_cap[w * 8 + c] record slots starting at
+  // cls_base[w * 8 + c] + (s - pop_off[c]) * cls_cap[w * 8 + c]; unused
+  // slots have delay 0.  outdeg[s] counts the sender's real synapses.
+  bool padded = false;
+  std::vector<uint64_t> cls_base;
+  std::vector<uint32_t> cls_cap;
+  std::vector<uint32_t> outdeg;
+  uint64_t nrec = 0;                 // record slots (== nsyn unless padded)
   std::vector<uint64_t> rec8;        // plain: w_q | (target << 6 | delay) << 32
   std::vector<uint16_t> tgt16;       // compressed streams
   std::vector<int16_t> w16;
@@ -127,12 +136,16 @@ extern const uint32_t kKext[8];
 
 // Sampler (builder.cpp).  Rows are split into target windows of win_size
 // neurons aligned in the coordinate win_origin + local id (win_size >= 2^26:
-// one segment per sender).  Plain records hold instance-local targets (the
-// runtime offsets them by the instance's first global id on upload);
-// compressed records hold the target's offset inside its window (< 2^16).
+// one segment per sender); `pad` selects the fixed-capacity layout.  Plain
+// records hold instance-local targets (the runtime offsets them by the
+// instance's first global id on upload); compressed records hold the
+// target's offset inside its window (< 2^16).
 int sample_instance(const snn_instance_cfg &cfg, uint32_t syn_format, uint32_t win_size,
-                    uint32_t win_origin, int threads, HostInstance &out, std::string &err);
+                    uint32_t win_origin, bool pad, int threads, HostInstance &out,
+                    std::string &err);
 // Population sizes of an instance (for placement before sampling).
 uint32_t instance_neurons(const snn_instance_cfg &cfg);
+// Longest thalamic count table of an instance's populations.
+uint32_t thalamic_table_max(const snn_instance_cfg &cfg);
 
 }  // namespace snn

@@ -94,6 +94,8 @@ SIGNATURES = {
     "snn_time_steps": (C.c_int, [C.c_void_p, C.c_uint64, C.POINTER(C.c_double)]),
     "snn_sample_network": (C.c_int, [C.POINTER(_Inst), C.c_uint32, C.c_int32,
                                      C.POINTER(C.POINTER(_HostNet))]),
+    "snn_sample_network_windows": (C.c_int, [C.POINTER(_Inst), C.c_uint32, C.c_uint32, C.c_int32,
+                                             C.POINTER(C.POINTER(_HostNet))]),
     "snn_free_network": (None, [C.POINTER(_HostNet)]),
 }
 
@@ -287,14 +289,15 @@ class Simulator:
         return {f: getattr(inf, f) for f, _ in _Info._fields_}
 
 
-def sample_network(instance: Instance, syn_format="plain", host_threads=0):
-    """The network snn_build would upload, sampled on the host (no GPU)."""
+def sample_network(instance: Instance, syn_format="plain", host_threads=0, window=0):
+    """The network snn_build would upload, sampled on the host (no GPU).
+    window = 256 or 512 reads it back from the LDS engine's storage layout."""
     keep = []
     s = _Inst()
     instance.fill(s, keep)
     p = C.POINTER(_HostNet)()
-    _check(lib().snn_sample_network(C.byref(s), _syn_format(syn_format), int(host_threads),
-                                    C.byref(p)))
+    _check(lib().snn_sample_network_windows(C.byref(s), _syn_format(syn_format), int(window),
+                                            int(host_threads), C.byref(p)))
     try:
         net = p.contents
         n, m = net.n_neurons, net.n_synapses

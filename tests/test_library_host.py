@@ -117,6 +117,32 @@ def test_sampler_equals_oracle(P, oracle, fmt, wmode, scale, mode, seed):
         np.testing.assert_array_equal(a["w_q"][k1], wq[k2])
 
 
+@pytest.mark.parametrize("window", [256, 512])
+@pytest.mark.parametrize("fmt,wmode", [("plain", 0), ("compressed", 1)])
+def test_windowed_layout_holds_the_oracle_network(P, oracle, window, fmt, wmode):
+    """The LDS engine's layout (fixed-capacity segments per sender and target
+    window, unused slots marked by delay 0) read back gives every row of the
+    oracle's network, as a multiset, and nothing else."""
+    scale, mode, seed = 0.04, 1, 4
+    a = P.sample_network(P.Instance(scale=scale, indegree_mode=mode, seed=seed), fmt, window=window)
+    net = oracle.Net(oracle.Config(scale=scale, indegree_mode=mode, seed=seed, weight_mode=wmode))
+    rp, post, d, w, wq = net.csr()
+    assert a["nsyn"] == net.nsyn
+    np.testing.assert_array_equal(a["row_ptr"], rp)
+    pre = np.repeat(np.arange(net.N), np.diff(rp).astype(np.int64))
+    k1 = np.lexsort((a["w_q"], a["delay"], a["post"], pre))
+    k2 = np.lexsort((wq, d, post, pre))
+    np.testing.assert_array_equal(a["post"][k1], post[k2])
+    np.testing.assert_array_equal(a["delay"][k1], d[k2])
+    np.testing.assert_array_equal(a["w_q"][k1], wq[k2])
+    # rows are ordered by target window
+    win = a["post"].astype(np.int64) // window
+    same_row = pre[1:] == pre[:-1]
+    assert np.all(win[1:][same_row] >= win[:-1][same_row])
+    with pytest.raises(P.SnnError, match="INVAL"):
+        P.sample_network(P.Instance(scale=0.01), fmt, window=100)
+
+
 def test_sampler_independent_of_thread_count(P):
     a = P.sample_network(P.Instance(scale=0.05, seed=2), "plain", host_threads=1)
     b = P.sample_network(P.Instance(scale=0.05, seed=2), "plain", host_threads=7)
