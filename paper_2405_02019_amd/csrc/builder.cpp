@@ -300,8 +300,21 @@ int sample_instance(const snn_instance_cfg &cfg, uint32_t syn_format, uint32_t w
   }
 
   const uint64_t R = out.nrec;
-  if (comp) {
-    out.rec8.clear();
+  // Compressed records of the padded layout pack into one 32-bit word: the
+  // 16-bit weight, the delay (6 bits) and the offset in the window (10 bits).
+  const bool pack4 = comp && pad;
+  if (pack4 && win_size > 1024) {
+    err = "packed compressed records need target windows of at most 1,024 neurons";
+    return SNN_E_RANGE;
+  }
+  out.rec8.clear();
+  out.rec4.clear();
+  out.tgt16.clear();
+  out.w16.clear();
+  out.d8.clear();
+  if (pack4) {
+    out.rec4.assign(R, 0);
+  } else if (comp) {
     out.tgt16.assign(R, 0);
     out.w16.assign(R, 0);
     out.d8.assign(R, 0);
@@ -341,9 +354,14 @@ int sample_instance(const snn_instance_cfg &cfg, uint32_t syn_format, uint32_t w
           bad.store(2);
           continue;
         }
-        out.tgt16[pos] = uint16_t((uint64_t(win_origin) + post) % win_size);
-        out.w16[pos] = int16_t(q);
-        out.d8[pos] = uint8_t(d);
+        const uint32_t off = uint32_t((uint64_t(win_origin) + post) % win_size);
+        if (pack4) {
+          out.rec4[pos] = (uint32_t(uint16_t(int16_t(q))) << 16) | (d << 10) | off;
+        } else {
+          out.tgt16[pos] = uint16_t(off);
+          out.w16[pos] = int16_t(q);
+          out.d8[pos] = uint8_t(d);
+        }
         wq = int32_t(q) * 8;
       } else {
         const double q = std::nearbyint(w * 256.0);

@@ -19,6 +19,10 @@ constexpr uint32_t kMetaLds = 512;
 constexpr uint32_t kLdsNeurons = 131072;
 constexpr uint32_t kLdsTab = 32;
 constexpr uint32_t kWinClasses = 16;
+// Flag and list slots of the LDS engine: a block publishes step t only after
+// every block it reads from has published step t-2, so four slots are never
+// overwritten while a reader still needs them.
+constexpr uint32_t kSlots = 4;
 
 // One sender class as seen from one target window: senders [first, first + n)
 // (global ids) own `cap` record slots each in the window, the first at `base`.
@@ -68,6 +72,7 @@ struct DeviceNet {
   int32_t *W = nullptr;             // [64][ntot]
   const uint64_t *seg_ptr = nullptr;
   const uint64_t *rec8 = nullptr;
+  const uint32_t *rec4 = nullptr;   // LDS engine, compressed: w16 << 16 | delay << 10 | offset
   const uint16_t *tgt16 = nullptr;
   const int16_t *w16 = nullptr;
   const uint8_t *d8 = nullptr;
@@ -83,8 +88,8 @@ struct DeviceNet {
   const WinClass *wcls = nullptr;   // LDS engine: [windows][kWinClasses]
   const uint2 *wrel = nullptr;      // LDS engine: per window, the blocks [x, y) that reach it
   const uint32_t *outdeg = nullptr; // LDS engine: synapses per sender [ntot]
-  uint64_t *lflags = nullptr;       // LDS engine: [2][windows] flag words
-  uint32_t *llist = nullptr;        // LDS engine: [3][ntot] senders beyond the inline ones
+  uint64_t *lflags = nullptr;       // LDS engine: [kSlots][windows] flag words
+  uint32_t *llist = nullptr;        // LDS engine: [kSlots][ntot] senders beyond the inline ones
 };
 
 struct LaunchShape {

@@ -98,25 +98,15 @@ __device__ __forceinline__ uint32_t quad_code(const InstDev *__restrict__ ip, ui
   return c;
 }
 
-// eqn:mem and eqn:ref for step t, with the thalamic counts T_t of the quad
-// (packed one byte per neuron into tp).  tab/meta hold the thalamic tables;
-// meta[mbase + population] = (offset, length).  Returns a 4-bit spike mask.
-__device__ __forceinline__ uint32_t decide_quad(const uint32_t *tab, const uint2 *meta,
-                                                uint32_t mbase, uint64_t seed, uint32_t lq,
-                                                uint32_t code, uint64_t t, Props k,
-                                                float (&u)[4], const float (&i)[4], uint32_t &r4,
-                                                uint32_t &tp, uint32_t &tsum) {
-  const Philox4 x = philox4x32_10(lq, uint32_t(t), uint32_t(t >> 32), kStreamThalamic,
-                                  uint32_t(seed), uint32_t(seed >> 32));
-  uint32_t flags = 0, rout = 0, tpk = 0;
+// eqn:mem and eqn:ref for step t: the membrane update of the quad's real
+// neurons (bit 12 + m of code).  Returns a 4-bit spike mask.
+__device__ __forceinline__ uint32_t lif_quad(uint32_t code, Props k, float (&u)[4],
+                                             const float (&i)[4], uint32_t &r4) {
+  uint32_t flags = 0, rout = 0;
 #pragma unroll
   for (int m = 0; m < 4; ++m) {
     uint32_t r = (r4 >> (8 * m)) & 0xFFu;
     if ((code >> (12 + m)) & 1u) {
-      const uint2 mt = meta[mbase + ((code >> (3 * m)) & 7u)];
-      const uint32_t T = thalamic_count(tab, mt, x.v[m]);
-      tpk |= T << (8 * m);
-      tsum += T;
       if (r == 0) {
         const float a = k.p22 * u[m];
         const float b = k.p21 * i[m];
@@ -135,8 +125,31 @@ __device__ __forceinline__ uint32_t decide_quad(const uint32_t *tab, const uint2
     rout |= r << (8 * m);
   }
   r4 = rout;
-  tp = tpk;
   return flags;
+}
+
+// Step t of a quad: the thalamic counts T_t (packed one byte per neuron into
+// tp, their sum added to tsum) and the membrane update.  tab/meta hold the
+// thalamic tables; meta[mbase + population] = (offset, length).
+__device__ __forceinline__ uint32_t decide_quad(const uint32_t *tab, const uint2 *meta,
+                                                uint32_t mbase, uint64_t seed, uint32_t lq,
+                                                uint32_t code, uint64_t t, Props k,
+                                                float (&u)[4], const float (&i)[4], uint32_t &r4,
+                                                uint32_t &tp, uint32_t &tsum) {
+  const Philox4 x = philox4x32_10(lq, uint32_t(t), uint32_t(t >> 32), kStreamThalamic,
+                                  uint32_t(seed), uint32_t(seed >> 32));
+  uint32_t tpk = 0;
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    if ((code >> (12 + m)) & 1u) {
+      const uint2 mt = meta[mbase + ((code >> (3 * m)) & 7u)];
+      const uint32_t T = thalamic_count(tab, mt, x.v[m]);
+      tpk |= T << (8 * m);
+      tsum += T;
+    }
+  }
+  tp = tpk;
+  return lif_quad(code, k, u, i, r4);
 }
 
 // eqn:psc: I <- p11 I + (T w_ext + W) 2^-8, the input summed as an integer.
@@ -854,18 +867,20 @@ hipError_t launch_persistent(const DeviceNet &d, const LaunchShape &sh, uint32_t
 // Blocks exchange nothing but their senders.  Per step each block publishes
 // one 64-bit flag word: the step's epoch, its spike count and the window
 // offsets of its first four spikes (further ones go to a list in memory).
-// The flags are also the grid barrier: a block waits until every block whose
-// neurons can reach its window (the blocks of its own instances) has
-// published the step, and then holds their senders.  No atomics are used.
+// No atomics are involved.  Since every delay is at least one step, a spike
+// of step t first changes a decision at step t+2, so a block needs the
+// senders of step t-1 only after it has decided step t: the wait for the
+// other blocks' flags of step t-1 comes after the block's own decision of
+// step t, and the flags' propagation overlaps a whole step of work.  A block
+// reads the flags of the blocks that can reach its window (those of its own
+// instances) only; blocks of unrelated instances never wait for each other.
 //
 // Iteration it (t = t0 + it):
-//   (a) complete step t-1 from ring row t-1;
-//   issue the record loads of step t-1's senders (staged at the end of the
-//   previous iteration);
-//   (b) decide step t and publish the flag;
-//   (c) add the records into rows t .. t+62;
-//   wait for the step-t flags of the relevant blocks and stage the senders.
-// The record loads are in flight while (b) runs.
+//   (a) complete step t-1 from ring row t-1 and the thalamic counts T_{t-1};
+//   (b) decide step t (membrane update only) and publish its flag;
+//   (c) wait for the flags of step t-1, stage those senders, issue their
+//       record loads, draw the thalamic counts T_t while the loads are in
+//       flight, and add the records into rows t .. t+62.
 // ---------------------------------------------------------------------------
 constexpr uint32_t kInline = 4;  // senders carried in a flag word
 
@@ -876,83 +891,93 @@ __device__ __forceinline__ uint32_t flag_local(uint64_t f, uint32_t k) {
   return uint32_t(f >> (26 + 9 * k)) & 511u;
 }
 
-// Stages senders [j0, j0 + nb) of the current sender set (nonzero blocks in
-// s_nzf / s_nzp / s_nzb): the address of each sender's segment in this window
-// goes to s_sb, the exclusive prefix of the segment capacities to s_sx.
-// Returns the record slots of the batch.
+// Stages senders [j0, j0 + nb) of the current sender set (blocks with
+// senders in s_nzf / s_nzp / s_nzb): the address and capacity of each
+// sender's segment in this window go to s_sb / s_cap.
 template <int WN, int NC>
-__device__ __forceinline__ uint32_t stage_senders(const DeviceNet &d, uint32_t j0, uint32_t nb,
-                                                  uint32_t nnz, uint32_t lslot,
-                                                  const uint64_t *s_nzf, const uint32_t *s_nzp,
-                                                  const uint16_t *s_nzb, const WinClass *s_cls,
-                                                  uint64_t *s_sb, uint32_t *s_sx,
-                                                  uint32_t *s_tmp) {
+__device__ __forceinline__ void stage_senders(const DeviceNet &d, uint32_t j0, uint32_t nb,
+                                              uint32_t nnz, uint32_t lslot, const uint64_t *s_nzf,
+                                              const uint32_t *s_nzp, const uint16_t *s_nzb,
+                                              const WinClass *s_cls, uint64_t *s_sb,
+                                              uint32_t *s_cap) {
   const uint32_t tid = threadIdx.x;
+  if (tid >= nb) return;
+  const uint32_t j = j0 + tid;
+  uint32_t lo = 0, hi = nnz;
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (s_nzp[mid] <= j) lo = mid; else hi = mid;
+  }
+  const uint32_t kk = j - s_nzp[lo];
+  const uint32_t src = s_nzb[lo];
+  const uint32_t loc =
+      kk < kInline ? flag_local(s_nzf[lo], kk)
+                   : ld_ag(d.llist + size_t(lslot) * d.ntot + size_t(src) * WN + kk);
+  const uint32_t gid = src * WN + loc;
   uint32_t cap = 0;
   uint64_t base = 0;
-  if (tid < nb) {
-    const uint32_t j = j0 + tid;
-    uint32_t lo = 0, hi = nnz;
-    while (hi - lo > 1) {
-      const uint32_t mid = (lo + hi) >> 1;
-      if (s_nzp[mid] <= j) lo = mid; else hi = mid;
-    }
-    const uint32_t kk = j - s_nzp[lo];
-    const uint32_t src = s_nzb[lo];
-    const uint32_t loc =
-        kk < kInline ? flag_local(s_nzf[lo], kk)
-                     : ld_ag(d.llist + size_t(lslot) * d.ntot + size_t(src) * WN + kk);
-    const uint32_t gid = src * WN + loc;
 #pragma unroll
-    for (int c = 0; c < NC; ++c) {
-      const uint32_t off = gid - s_cls[c].first;
-      if (off < s_cls[c].n) {
-        cap = s_cls[c].cap;
-        base = s_cls[c].base + uint64_t(off) * cap;
-      }
+  for (int c = 0; c < NC; ++c) {
+    const uint32_t off = gid - s_cls[c].first;
+    if (off < s_cls[c].n) {
+      cap = s_cls[c].cap;
+      base = s_cls[c].base + uint64_t(off) * cap;
     }
   }
-  uint32_t total;
-  const uint32_t ex = block_exclusive_scan<256>(cap, s_tmp, total);
   s_sb[tid] = base;
-  s_sx[tid] = ex;
-  __syncthreads();
-  return total;
+  s_cap[tid] = cap;
 }
 
-// Up to UR record slots per thread: slot e = e0 + threadIdx.x + u * 256 of the
-// staged batch.  load() issues the loads, apply() adds the records into the
-// ring rows (t_src + delay); empty slots (delay 0) are skipped.
+// UR record slots per lane.  load() walks this wave's senders of the staged
+// batch (senders wave, wave + 4, ...; lane l holds the segment address and
+// capacity of the wave's sender l) in 64-record pieces, one piece per slot;
+// apply() adds the loaded records into rows (t_src + delay).  Unused slots
+// and empty record slots (delay 0) add nothing.
 template <bool COMP, int UR>
-struct RecordBatch {
+struct SegmentWalk {
   uint64_t rec[COMP ? 1 : UR];
-  uint32_t tw[COMP ? UR : 1];   // compressed: target offset | weight << 16
-  uint32_t dl[COMP ? UR : 1];
+  uint32_t r4[COMP ? UR : 1];
+  uint64_t base_l;   // lane l: segment of the wave's sender l
+  uint32_t cap_l;
+  uint32_t nl;       // senders of this wave
+  uint32_t l, c0;    // cursor: sender, offset in its segment
+  uint32_t cap;
+  uint64_t base;
 
-  __device__ __forceinline__ void load(const DeviceNet &d, const uint64_t *s_sb,
-                                       const uint32_t *s_sx, uint32_t nb, uint32_t e0,
-                                       uint32_t total) {
+  __device__ __forceinline__ void begin(const uint64_t *s_sb, const uint32_t *s_cap, uint32_t nb) {
+    const uint32_t wave = threadIdx.x >> 6, lane = __lane_id();
+    const uint32_t jl = wave + 4u * lane;
+    base_l = jl < nb ? s_sb[jl] : 0ull;
+    cap_l = jl < nb ? s_cap[jl] : 0u;
+    nl = nb > wave ? (nb - wave + 3u) / 4u : 0u;
+    l = 0;
+    c0 = 0;
+    cap = __builtin_amdgcn_readfirstlane(cap_l);
+    base = (uint64_t(__builtin_amdgcn_readfirstlane(uint32_t(base_l >> 32))) << 32) |
+           __builtin_amdgcn_readfirstlane(uint32_t(base_l));
+  }
+  __device__ __forceinline__ bool more() const { return l < nl; }
+
+  __device__ __forceinline__ void load(const DeviceNet &d) {
+    const uint32_t lane = __lane_id();
 #pragma unroll
     for (int u = 0; u < UR; ++u) {
-      const uint32_t e = e0 + threadIdx.x + uint32_t(u) * 256u;
-      uint64_t idx = 0;
-      const bool ok = e < total;
-      if (ok) {
-        uint32_t lo = 0, hi = nb;
-        while (hi - lo > 1) {
-          const uint32_t mid = (lo + hi) >> 1;
-          if (s_sx[mid] <= e) lo = mid; else hi = mid;
+      while (l < nl && c0 >= cap) {
+        ++l;
+        c0 = 0;
+        if (l < nl) {
+          cap = __builtin_amdgcn_readlane(cap_l, l);
+          base = (uint64_t(__builtin_amdgcn_readlane(uint32_t(base_l >> 32), l)) << 32) |
+                 __builtin_amdgcn_readlane(uint32_t(base_l), l);
         }
-        idx = s_sb[lo] + (e - s_sx[lo]);
       }
-      if (COMP) {
-        tw[u] = ok ? uint32_t(__builtin_nontemporal_load(d.tgt16 + idx)) |
-                         (uint32_t(uint16_t(__builtin_nontemporal_load(d.w16 + idx))) << 16)
-                   : 0u;
-        dl[u] = ok ? uint32_t(__builtin_nontemporal_load(d.d8 + idx)) : 0u;
-      } else {
+      const bool ok = l < nl && c0 + lane < cap;
+      const uint64_t idx = base + c0 + lane;
+      if (COMP)
+        r4[u] = ok ? __builtin_nontemporal_load(d.rec4 + idx) : 0u;
+      else
         rec[u] = ok ? __builtin_nontemporal_load(d.rec8 + idx) : 0ull;
-      }
+      c0 += 64;
     }
   }
 
@@ -963,9 +988,9 @@ struct RecordBatch {
       uint32_t delay, loc;
       int32_t wq;
       if (COMP) {
-        delay = dl[u];
-        loc = tw[u] & 0xFFFFu;
-        wq = int32_t(int16_t(tw[u] >> 16)) * 8;
+        delay = (r4[u] >> 10) & 63u;
+        loc = r4[u] & 1023u;
+        wq = int32_t(int16_t(uint16_t(r4[u] >> 16))) * 8;
       } else {
         const uint32_t hiw = uint32_t(rec[u] >> 32);
         delay = hiw & 63u;
@@ -980,14 +1005,18 @@ struct RecordBatch {
 template <int WN, bool COMP>
 __global__ __launch_bounds__(256) void k_lds(DeviceNet d, uint32_t n_steps, uint32_t spin_limit) {
   constexpr uint32_t BS = 256;
-  constexpr uint32_t NQ = WN / 4;             // quads of the window (one per thread)
+  constexpr uint32_t NQ = WN / 4;             // quads of the window
+  constexpr uint32_t Q0 = BS - NQ;            // threads Q0.. own one quad each
+  constexpr uint32_t NPT = WN / BS;           // neurons per thread in the thalamic draw
   constexpr int NSLOT = WN / 256;             // instances a window can overlap
   constexpr int NC = 8 * NSLOT;               // sender classes that can reach it
   constexpr uint32_t TS = kLdsTab + 8;        // stride of an LDS thalamic table
   constexpr uint32_t NZ = kLdsNeurons / WN;   // largest grid of this window size
   constexpr int NJ = NZ / 64;                 // flags per lane of the polling wave
   constexpr uint32_t RC = WN + 128;           // raster staging entries
-  constexpr int UR = 8;                       // record loads in flight per thread
+  constexpr uint32_t SB = BS;                 // senders staged per batch
+  constexpr int UR = 8;                       // record pieces in flight per lane
+  static_assert(Q0 >= 64, "wave 0 polls; it owns no quad");
   __shared__ int32_t s_ring[kRing * WN];
   __shared__ uint32_t s_thr[NSLOT * 8 * TS];
   __shared__ uint2 s_meta[NSLOT * 8];
@@ -995,18 +1024,20 @@ __global__ __launch_bounds__(256) void k_lds(DeviceNet d, uint32_t n_steps, uint
   __shared__ uint64_t s_nzf[NZ];
   __shared__ uint32_t s_nzp[NZ];
   __shared__ uint16_t s_nzb[NZ];
-  __shared__ uint64_t s_sb[BS];
-  __shared__ uint32_t s_sx[BS];
+  __shared__ uint64_t s_sb[SB];
+  __shared__ uint32_t s_cap[SB];
   __shared__ uint64_t s_rast[RC];
-  __shared__ uint32_t s_tmp[BS / 64], s_wave[BS / 64], s_inl[kInline];
-  __shared__ uint32_t s_inst[NSLOT], s_flag, s_n, s_nnz, s_cnt;
+  __shared__ uint32_t s_T[NQ];                // T_t of each quad, one byte per neuron
+  __shared__ uint32_t s_wave[BS / 64], s_inl[kInline];
+  __shared__ uint32_t s_inst[NSLOT], s_flag, s_n, s_nnz;
   __shared__ unsigned long long s_rbase;
 
   const uint32_t G = gridDim.x, blk = blockIdx.x;
   const uint32_t tid = threadIdx.x, wave = tid >> 6, lane = __lane_id();
   const uint32_t wb0 = blk * WN;
-  const uint32_t q = wb0 / 4 + tid;
-  const bool owner = tid < NQ && q < d.nquads;
+  const uint32_t oq = tid - Q0;                              // owned quad in the window
+  const uint32_t q = wb0 / 4 + oq;
+  const bool owner = tid >= Q0 && q < d.nquads;
   const uint64_t t0 = d.ctl->t_base;
   const uint32_t ep0 = d.ctl->epoch;
   const Props k{d.consts->p11, d.consts->p22, d.consts->p21};
@@ -1036,11 +1067,35 @@ __global__ __launch_bounds__(256) void k_lds(DeviceNet d, uint32_t n_steps, uint
     s_meta[slot * 8 + p] = make_uint2(off, m.y);
   }
 
+  // Thalamic draw: thread tid handles neurons NPT tid .. NPT tid + NPT - 1 of
+  // the window (one quad's Philox block); tmeta = s_meta index or 0xFF.
+  uint32_t d_lq = 0, tmeta = 0xFFFFFFFFu;
+  uint64_t d_seed = 0;
+  {
+    const uint32_t n0 = wb0 + NPT * tid;
+    const uint32_t dq = n0 / 4;
+    if (dq < d.nquads) {
+      const uint32_t qi = d.qinfo[dq];
+      const InstDev *ip = d.inst + (qi >> 24);
+      d_lq = qi & 0xFFFFFFu;
+      d_seed = ip->seed;
+      const uint32_t code = quad_code(ip, d_lq);
+      const uint32_t sl = NSLOT > 1 && (qi >> 24) != s_inst[0] ? 1u : 0u;
+      tmeta = 0;
+#pragma unroll
+      for (uint32_t i = 0; i < NPT; ++i) {
+        const uint32_t m = (n0 + i) & 3u;
+        const uint32_t v = ((code >> (12 + m)) & 1u) ? sl * 8u + ((code >> (3 * m)) & 7u) : 0xFFu;
+        tmeta |= v << (8 * i);
+      }
+    }
+  }
+
   float U[4] = {0, 0, 0, 0}, I[4] = {0, 0, 0, 0};
-  uint32_t R = 0, Tp = 0, QI = 0, PC = 0, slot = 0, c_spk = 0, c_poi = 0;
+  uint32_t R = 0, PC = 0, c_spk = 0, c_poi = 0;
   uint32_t OD[4] = {0, 0, 0, 0};
   int64_t c_con = 0;
-  uint64_t c_ev = 0, seed = 0;
+  uint64_t c_ev = 0;
   int32_t wext = 0;
   if (owner) {
     const float4 uv = ld4(d.U + 4 * size_t(q));
@@ -1048,16 +1103,14 @@ __global__ __launch_bounds__(256) void k_lds(DeviceNet d, uint32_t n_steps, uint
     U[0] = uv.x; U[1] = uv.y; U[2] = uv.z; U[3] = uv.w;
     I[0] = iv.x; I[1] = iv.y; I[2] = iv.z; I[3] = iv.w;
     R = d.R4[q];
-    QI = d.qinfo[q];
-    const InstDev *ip = d.inst + (QI >> 24);
-    PC = quad_code(ip, QI & 0xFFFFFFu);
-    seed = ip->seed;
+    const uint32_t qi = d.qinfo[q];
+    const InstDev *ip = d.inst + (qi >> 24);
+    PC = quad_code(ip, qi & 0xFFFFFFu);
     wext = ip->w_ext_q;
     const uint4 od = *reinterpret_cast<const uint4 *>(d.outdeg + 4 * size_t(q));
     OD[0] = od.x; OD[1] = od.y; OD[2] = od.z; OD[3] = od.w;
   }
   __syncthreads();
-  if (owner) slot = NSLOT > 1 && (QI >> 24) != s_inst[0] ? 1u : 0u;
 
   // Flushes the staged raster entries to the device raster.
   uint32_t rn = 0;
@@ -1077,61 +1130,82 @@ __global__ __launch_bounds__(256) void k_lds(DeviceNet d, uint32_t n_steps, uint
     rn = 0;
   };
 
-  uint32_t n_prev = 0, nnz = 0, tot0 = 0;
+  // Thalamic counts T_t of this thread's neurons into s_T (byte per neuron).
+  auto draw_thalamic = [&](uint64_t t) {
+    if (tmeta == 0xFFFFFFFFu) return;
+    const Philox4 x = philox4x32_10(d_lq, uint32_t(t), uint32_t(t >> 32), kStreamThalamic,
+                                    uint32_t(d_seed), uint32_t(d_seed >> 32));
+    uint32_t packed = 0;
+#pragma unroll
+    for (uint32_t i = 0; i < NPT; ++i) {
+      const uint32_t mi = (tmeta >> (8 * i)) & 0xFFu;
+      const uint32_t m = (NPT * tid + i) & 3u;
+      const uint32_t u = m == 0 ? x.v[0] : m == 1 ? x.v[1] : m == 2 ? x.v[2] : x.v[3];
+      const uint32_t T = mi == 0xFFu ? 0u : thalamic_count(s_thr, s_meta[mi], u);
+      packed |= T << (8 * i);
+    }
+    if (NPT == 1)
+      reinterpret_cast<uint8_t *>(s_T)[tid] = uint8_t(packed);
+    else
+      reinterpret_cast<uint16_t *>(s_T)[tid] = uint16_t(packed);
+  };
+
   for (uint32_t it = 0; it <= n_steps; ++it) {
     const uint64_t t = t0 + it;
     const bool decide = it < n_steps;
-    const uint32_t ep = ep0 + it + 1;         // epoch of step t's publication
-    const uint32_t lslot_prev = (ep - 1) % 3; // list of step t-1's senders
+    const uint32_t ep = ep0 + it + 1;         // epoch of step t's flags
+    const uint32_t epp = ep - 1;              // epoch of step t-1's flags
+    const uint64_t *fs = flags + size_t(epp % kSlots) * G;
 
-    // (a) complete step t-1 from ring row t-1.
+    // Wave 0 issues the flag loads of step t-1 now; they are checked in (c).
+    uint64_t fv[NJ];
+    if (wave == 0 && it > 0) {
+#pragma unroll
+      for (int j = 0; j < NJ; ++j) {
+        const uint32_t bb = rel.x + lane + 64u * uint32_t(j);
+        fv[j] = bb < rel.y ? ld_ag(fs + bb) : 0ull;
+      }
+    }
+
+    // (a) complete step t-1 from ring row t-1 and T_{t-1}.
     if (it > 0 && owner) {
-      int32_t *row = s_ring + ((t - 1) & (kRing - 1)) * WN + 4 * tid;
+      int32_t *row = s_ring + ((t - 1) & (kRing - 1)) * WN + 4 * oq;
+      const uint32_t Tp = s_T[oq];
 #pragma unroll
       for (int m = 0; m < 4; ++m) {
         const int32_t w = row[m];
         row[m] = 0;
         if ((PC >> (12 + m)) & 1u) {
-          I[m] = next_current(I[m], int32_t((Tp >> (8 * m)) & 0xFFu), wext, w, k.p11);
+          const int32_t T = int32_t((Tp >> (8 * m)) & 0xFFu);
+          I[m] = next_current(I[m], T, wext, w, k.p11);
           c_con += w;
+          c_poi += uint32_t(T);
         }
       }
     }
 
-    // Record loads of step t-1's senders (batch 0, staged at the end of the
-    // previous iteration); they stay in flight during (b).
-    RecordBatch<COMP, UR> rb;
-    if (n_prev) rb.load(d, s_sb, s_sx, min(n_prev, BS), 0, tot0);
-
     // (b) decide step t and publish its senders.
     if (decide) {
-      uint32_t fl = 0;
-      if (owner)
-        fl = decide_quad(s_thr, s_meta, slot * 8u, seed, QI & 0xFFFFFFu, PC, t, k, U, I, R, Tp,
-                         c_poi);
+      const uint32_t fl = owner ? lif_quad(PC, k, U, I, R) : 0u;
       uint32_t lo, tot;
       wave_compact(fl, lo, tot);
       if (lane == 0) s_wave[wave] = tot;
       __syncthreads();
-      if (tid == 0) {
-        uint32_t run = 0;
-        for (uint32_t w = 0; w < BS / 64; ++w) {
-          const uint32_t c = s_wave[w];
-          s_wave[w] = run;
-          run += c;
-        }
-        s_cnt = run;
+      uint32_t before = 0, cnt = 0;
+#pragma unroll
+      for (uint32_t w = 0; w < BS / 64; ++w) {
+        const uint32_t c = s_wave[w];
+        before += w < wave ? c : 0u;
+        cnt += c;
       }
-      __syncthreads();
-      const uint32_t cnt = s_cnt;
       if (fl) {
-        uint32_t p = s_wave[wave] + lo;
-        uint32_t *lst = d.llist + size_t(ep % 3) * d.ntot + wb0;
+        uint32_t p = before + lo;
+        uint32_t *lst = d.llist + size_t(ep % kSlots) * d.ntot + wb0;
         c_spk += __popc(fl);
 #pragma unroll
         for (int m = 0; m < 4; ++m) {
           if (!((fl >> m) & 1u)) continue;
-          const uint32_t loc = 4 * tid + uint32_t(m);
+          const uint32_t loc = 4 * oq + uint32_t(m);
           if (p < kInline)
             s_inl[p] = loc;
           else
@@ -1148,41 +1222,20 @@ __global__ __launch_bounds__(256) void k_lds(DeviceNet d, uint32_t n_steps, uint
         uint64_t f = uint64_t(ep & 0xFFFFu) | (uint64_t(cnt) << 16);
         for (uint32_t kk = 0; kk < kInline && kk < cnt; ++kk)
           f |= uint64_t(s_inl[kk]) << (26 + 9 * kk);
-        st_ag(flags + size_t(ep & 1u) * G + blk, f);
+        st_ag(flags + size_t(ep % kSlots) * G + blk, f);
       }
       rn += cnt;
       if (rn > RC - WN) flush();
     }
 
-    // (c) step t-1's senders into rows t .. t+62.
-    if (n_prev) {
-      const uint64_t tsrc = t - 1;
-      rb.template apply<WN>(s_ring, tsrc, wb0);
-      const uint32_t nb0 = min(n_prev, BS);
-      for (uint32_t e0 = BS * UR; e0 < tot0; e0 += BS * UR) {
-        RecordBatch<COMP, UR> r2;
-        r2.load(d, s_sb, s_sx, nb0, e0, tot0);
-        r2.template apply<WN>(s_ring, tsrc, wb0);
-      }
-      for (uint32_t j0 = BS; j0 < n_prev; j0 += BS) {
-        __syncthreads();
-        const uint32_t nb = min(BS, n_prev - j0);
-        const uint32_t tot = stage_senders<WN, NC>(d, j0, nb, nnz, lslot_prev, s_nzf, s_nzp, s_nzb,
-                                                   s_cls, s_sb, s_sx, s_tmp);
-        for (uint32_t e0 = 0; e0 < tot; e0 += BS * UR) {
-          RecordBatch<COMP, UR> r2;
-          r2.load(d, s_sb, s_sx, nb, e0, tot);
-          r2.template apply<WN>(s_ring, tsrc, wb0);
-        }
-      }
+    if (it == 0) {   // nothing to deliver yet
+      draw_thalamic(t);
+      __syncthreads();
+      continue;
     }
-    if (!decide) break;
 
-    // Wait for step t's flags of the relevant blocks; collect their senders.
-    __syncthreads();
+    // (c) wait for step t-1's flags; collect the blocks that have senders.
     if (wave == 0) {
-      uint64_t fv[NJ];
-      const uint64_t *fs = flags + size_t(ep & 1u) * G;
       uint32_t spins = 0;
       bool ok = true;
       for (;;) {
@@ -1190,10 +1243,9 @@ __global__ __launch_bounds__(256) void k_lds(DeviceNet d, uint32_t n_steps, uint
 #pragma unroll
         for (int j = 0; j < NJ; ++j) {
           const uint32_t bb = rel.x + lane + 64u * uint32_t(j);
-          fv[j] = 0;
-          if (bb < rel.y) {
+          if (bb < rel.y && (uint32_t(fv[j]) & 0xFFFFu) != (epp & 0xFFFFu)) {
             fv[j] = ld_ag(fs + bb);
-            mine = mine && (uint32_t(fv[j]) & 0xFFFFu) == (ep & 0xFFFFu);
+            mine = mine && (uint32_t(fv[j]) & 0xFFFFu) == (epp & 0xFFFFu);
           }
         }
         if (__all(mine)) break;
@@ -1211,7 +1263,7 @@ __global__ __launch_bounds__(256) void k_lds(DeviceNet d, uint32_t n_steps, uint
         nzc += c ? 1u : 0u;
         sc += c;
       }
-      // inclusive wave scan of (senders << 10 | nonzero blocks)
+      // inclusive wave scan of (senders << 10 | blocks with senders)
       const uint32_t v = (sc << 10) | nzc;
       uint32_t x = v;
 #pragma unroll
@@ -1240,12 +1292,30 @@ __global__ __launch_bounds__(256) void k_lds(DeviceNet d, uint32_t n_steps, uint
     }
     __syncthreads();
     if (!s_flag) break;
-    n_prev = s_n;
-    nnz = s_nnz;
-    tot0 = 0;
-    if (n_prev)
-      tot0 = stage_senders<WN, NC>(d, 0, min(n_prev, BS), nnz, ep % 3, s_nzf, s_nzp, s_nzb, s_cls,
-                                   s_sb, s_sx, s_tmp);
+    const uint32_t n_prev = s_n, nnz = s_nnz;
+    const uint64_t tsrc = t - 1;
+    bool drawn = !decide;
+    for (uint32_t j0 = 0; j0 < n_prev; j0 += SB) {
+      const uint32_t nb = min(SB, n_prev - j0);
+      stage_senders<WN, NC>(d, j0, nb, nnz, epp % kSlots, s_nzf, s_nzp, s_nzb, s_cls, s_sb, s_cap);
+      __syncthreads();
+      SegmentWalk<COMP, UR> sw;
+      sw.begin(s_sb, s_cap, nb);
+      while (sw.more()) {
+        sw.load(d);
+        if (!drawn) {   // T_t while the first records are in flight
+          draw_thalamic(t);
+          drawn = true;
+        }
+        sw.template apply<WN>(s_ring, tsrc, wb0);
+      }
+      __syncthreads();
+    }
+    if (!drawn) {
+      draw_thalamic(t);
+      drawn = true;
+    }
+    __syncthreads();
   }
 
   // Raster, ring rows, state and counters back to memory.
@@ -1270,7 +1340,7 @@ __global__ __launch_bounds__(256) void k_lds(DeviceNet d, uint32_t n_steps, uint
       ev += __shfl_xor(ev, o);
       co += __shfl_xor(co, o);
     }
-    if (lane == 0 && tid < NQ && q < d.nquads) {
+    if (lane == 0 && tid >= Q0 && q < d.nquads) {
       int64_t *c = d.wave_ctr + 4 * size_t(q >> 6);
       c[0] += int64_t(sp);
       c[1] += int64_t(po);

@@ -138,8 +138,9 @@ uint64_t spike_bound(const snn_net *h, uint64_t steps) {
 }
 
 // LDS engine: block b owns neurons [b W, (b+1) W) with their 64 ring rows in
-// LDS.  W = 512 (one block per CU) when the network fits, else W = 256 (two
-// blocks per CU); 0 when neither fits the co-resident grid.
+// LDS.  W = 256 (two blocks per CU: more blocks share the delivery work) when
+// the network fits, else W = 512; a requested grid size selects the window
+// that gives it.  0 when neither fits the co-resident grid.
 uint32_t lds_capacity() {
   const int g512 = lds_max_grid(512), g256 = lds_max_grid(256);
   return uint32_t(std::max(int64_t(g512) * 512, int64_t(g256) * 256));
@@ -147,7 +148,7 @@ uint32_t lds_capacity() {
 
 uint32_t choose_lds_window(uint32_t ntot, uint32_t block, uint32_t grid) {
   if (block && block != 256) return 0;
-  for (uint32_t w : {512u, 256u}) {
+  for (uint32_t w : {256u, 512u}) {
     const uint32_t g = (ntot + w - 1) / w;
     if (grid && grid != g) continue;
     if (int64_t(g) <= int64_t(lds_max_grid(w))) return w;
@@ -360,6 +361,7 @@ int snn_build(const snn_config *cfg, snn_net **out) {
   uint2 *d_pmeta;
   uint64_t *d_seg, *d_rec8 = nullptr;
   uint16_t *d_tgt16 = nullptr;
+  uint32_t *d_rec4 = nullptr;
   int16_t *d_w16 = nullptr;
   uint8_t *d_d8 = nullptr;
   const bool comp = cfg->syn_format == SNN_SYN_COMPRESSED5;
@@ -382,7 +384,9 @@ int snn_build(const snn_config *cfg, snn_net **out) {
   ALLOC(d.R4, d.nquads);
   ALLOC(d.W, size_t(kRing) * d.ntot);
   ALLOC(d_seg, nseg_tot + 1);
-  if (comp) {
+  if (comp && lds_window) {
+    ALLOC(d_rec4, std::max<uint64_t>(1, nrec_tot));
+  } else if (comp) {
     ALLOC(d_tgt16, std::max<uint64_t>(1, nrec_tot));
     ALLOC(d_w16, std::max<uint64_t>(1, nrec_tot));
     ALLOC(d_d8, std::max<uint64_t>(1, nrec_tot));
@@ -404,8 +408,8 @@ int snn_build(const snn_config *cfg, snn_net **out) {
     ALLOC(d_wcls, size_t(nwin_lds) * kWinClasses);
     ALLOC(d_wrel, nwin_lds);
     ALLOC(d_outdeg, d.ntot);
-    ALLOC(d.lflags, 2 * size_t(nwin_lds));
-    ALLOC(d.llist, 3 * size_t(d.ntot));
+    ALLOC(d.lflags, kSlots * size_t(nwin_lds));
+    ALLOC(d.llist, kSlots * size_t(d.ntot));
   }
 #undef ALLOC
 
@@ -508,7 +512,9 @@ int snn_build(const snn_config *cfg, snn_net **out) {
   syn_base = 0;
   for (uint32_t k = 0; k < ni; ++k) {
     HostInstance &x = hi[k];
-    if (comp) {
+    if (comp && lds_window) {
+      UPLOAD(d_rec4 + syn_base, x.rec4.data(), x.nrec * sizeof(uint32_t));
+    } else if (comp) {
       UPLOAD(d_tgt16 + syn_base, x.tgt16.data(), x.nrec * sizeof(uint16_t));
       UPLOAD(d_w16 + syn_base, x.w16.data(), x.nrec * sizeof(int16_t));
       UPLOAD(d_d8 + syn_base, x.d8.data(), x.nrec * sizeof(uint8_t));
@@ -531,6 +537,7 @@ int snn_build(const snn_config *cfg, snn_net **out) {
   d.thr_lds = (nthr <= kThrLds && size_t(ni) * 8 <= kMetaLds) ? 1u : 0u;
   d.seg_ptr = d_seg;
   d.rec8 = d_rec8;
+  d.rec4 = d_rec4;
   d.tgt16 = d_tgt16;
   d.w16 = d_w16;
   d.d8 = d_d8;
@@ -544,7 +551,7 @@ int snn_build(const snn_config *cfg, snn_net **out) {
       hipMemset(d.wave_ctr, 0, 4 * size_t(d.nquads / 64) * sizeof(int64_t)) != hipSuccess ||
       hipMemset(d.events, 0, ni * sizeof(uint64_t)) != hipSuccess ||
       hipMemset(d.ctl, 0, sizeof(Control)) != hipSuccess ||
-      (d.lflags && hipMemset(d.lflags, 0, 2 * size_t(nwin_lds) * sizeof(uint64_t)) != hipSuccess)) {
+      (d.lflags && hipMemset(d.lflags, 0, kSlots * size_t(nwin_lds) * sizeof(uint64_t)) != hipSuccess)) {
     fail(h, SNN_E_HIP, "device memset failed");
     return bail(SNN_E_HIP);
   }
@@ -786,7 +793,12 @@ int snn_sample_network_windows(const snn_instance_cfg *inst, uint32_t syn_format
       for (uint64_t e2 = lo; e2 < hi; ++e2) {
         uint32_t post, dl;
         int32_t wq;
-        if (comp) {
+        if (comp && x.padded) {
+          const uint32_t r = x.rec4[e2];
+          post = (x.win_first + w) * x.win_size + (r & 1023u) - x.win_origin;
+          dl = (r >> 10) & 63u;
+          wq = int32_t(int16_t(uint16_t(r >> 16))) * 8;
+        } else if (comp) {
           post = (x.win_first + w) * x.win_size + x.tgt16[e2] - x.win_origin;
           dl = x.d8[e2];
           wq = int32_t(x.w16[e2]) * 8;

@@ -116,6 +116,7 @@ struct HostInstance {
   std::vector<uint32_t> outdeg;
   uint64_t nrec = 0;                 // record slots (== nsyn unless padded)
   std::vector<uint64_t> rec8;        // plain: w_q | (target << 6 | delay) << 32
+  std::vector<uint32_t> rec4;        // compressed, padded layout: w16 << 16 | delay << 10 | offset
   std::vector<uint16_t> tgt16;       // compressed streams
   std::vector<int16_t> w16;
   std::vector<uint8_t> d8;
