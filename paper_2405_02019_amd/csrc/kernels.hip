@@ -944,17 +944,21 @@ struct SegmentWalk {
   uint32_t cap;
   uint64_t base;
 
+  // nb must be wave-uniform.  All cursor state is scalar.
   __device__ __forceinline__ void begin(const uint64_t *s_sb, const uint32_t *s_cap, uint32_t nb) {
-    const uint32_t wave = threadIdx.x >> 6, lane = __lane_id();
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = __lane_id();
     const uint32_t jl = wave + 4u * lane;
     base_l = jl < nb ? s_sb[jl] : 0ull;
     cap_l = jl < nb ? s_cap[jl] : 0u;
     nl = nb > wave ? (nb - wave + 3u) / 4u : 0u;
     l = 0;
     c0 = 0;
-    cap = __builtin_amdgcn_readfirstlane(cap_l);
-    base = (uint64_t(__builtin_amdgcn_readfirstlane(uint32_t(base_l >> 32))) << 32) |
-           __builtin_amdgcn_readfirstlane(uint32_t(base_l));
+    pick(0);
+  }
+  __device__ __forceinline__ void pick(uint32_t i) {
+    cap = __builtin_amdgcn_readlane(cap_l, i);
+    base = (uint64_t(__builtin_amdgcn_readlane(uint32_t(base_l >> 32), i)) << 32) |
+           __builtin_amdgcn_readlane(uint32_t(base_l), i);
   }
   __device__ __forceinline__ bool more() const { return l < nl; }
 
@@ -965,11 +969,7 @@ struct SegmentWalk {
       while (l < nl && c0 >= cap) {
         ++l;
         c0 = 0;
-        if (l < nl) {
-          cap = __builtin_amdgcn_readlane(cap_l, l);
-          base = (uint64_t(__builtin_amdgcn_readlane(uint32_t(base_l >> 32), l)) << 32) |
-                 __builtin_amdgcn_readlane(uint32_t(base_l), l);
-        }
+        if (l < nl) pick(l);
       }
       const bool ok = l < nl && c0 + lane < cap;
       const uint64_t idx = base + c0 + lane;
@@ -1033,7 +1033,8 @@ __global__ __launch_bounds__(256) void k_lds(DeviceNet d, uint32_t n_steps, uint
   __shared__ unsigned long long s_rbase;
 
   const uint32_t G = gridDim.x, blk = blockIdx.x;
-  const uint32_t tid = threadIdx.x, wave = tid >> 6, lane = __lane_id();
+  const uint32_t tid = threadIdx.x, lane = __lane_id();
+  const uint32_t wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const uint32_t wb0 = blk * WN;
   const uint32_t oq = tid - Q0;                              // owned quad in the window
   const uint32_t q = wb0 / 4 + oq;
@@ -1194,7 +1195,7 @@ __global__ __launch_bounds__(256) void k_lds(DeviceNet d, uint32_t n_steps, uint
       uint32_t before = 0, cnt = 0;
 #pragma unroll
       for (uint32_t w = 0; w < BS / 64; ++w) {
-        const uint32_t c = s_wave[w];
+        const uint32_t c = __builtin_amdgcn_readfirstlane(s_wave[w]);
         before += w < wave ? c : 0u;
         cnt += c;
       }
@@ -1243,13 +1244,15 @@ __global__ __launch_bounds__(256) void k_lds(DeviceNet d, uint32_t n_steps, uint
 #pragma unroll
         for (int j = 0; j < NJ; ++j) {
           const uint32_t bb = rel.x + lane + 64u * uint32_t(j);
-          if (bb < rel.y && (uint32_t(fv[j]) & 0xFFFFu) != (epp & 0xFFFFu)) {
-            fv[j] = ld_ag(fs + bb);
-            mine = mine && (uint32_t(fv[j]) & 0xFFFFu) == (epp & 0xFFFFu);
-          }
+          mine = mine && (bb >= rel.y || (uint32_t(fv[j]) & 0xFFFFu) == (epp & 0xFFFFu));
         }
         if (__all(mine)) break;
         __builtin_amdgcn_s_sleep(1);
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) {   // reload every flag of the lane: one round trip
+          const uint32_t bb = rel.x + lane + 64u * uint32_t(j);
+          if (bb < rel.y) fv[j] = ld_ag(fs + bb);
+        }
         if ((++spins & 63u) == 0 && (ld_ag(&d.ctl->error) != 0 || spins > spin_limit)) {
           if (lane == 0) st_ag(&d.ctl->error, 2u);
           ok = false;
@@ -1291,8 +1294,9 @@ __global__ __launch_bounds__(256) void k_lds(DeviceNet d, uint32_t n_steps, uint
       }
     }
     __syncthreads();
-    if (!s_flag) break;
-    const uint32_t n_prev = s_n, nnz = s_nnz;
+    if (!__builtin_amdgcn_readfirstlane(s_flag)) break;
+    const uint32_t n_prev = __builtin_amdgcn_readfirstlane(s_n);
+    const uint32_t nnz = __builtin_amdgcn_readfirstlane(s_nnz);
     const uint64_t tsrc = t - 1;
     bool drawn = !decide;
     for (uint32_t j0 = 0; j0 < n_prev; j0 += SB) {
@@ -1304,6 +1308,8 @@ __global__ __launch_bounds__(256) void k_lds(DeviceNet d, uint32_t n_steps, uint
       while (sw.more()) {
         sw.load(d);
         if (!drawn) {   // T_t while the first records are in flight
+          // Keeps the draw from being scheduled ahead of the loads.
+          asm volatile("" : "+v"(d_lq) : : "memory");
           draw_thalamic(t);
           drawn = true;
         }
