@@ -891,46 +891,37 @@ __device__ __forceinline__ uint32_t flag_local(uint64_t f, uint32_t k) {
   return uint32_t(f >> (26 + 9 * k)) & 511u;
 }
 
-// Stages senders [j0, j0 + nb) of the current sender set (blocks with
-// senders in s_nzf / s_nzp / s_nzb): the address and capacity of each
-// sender's segment in this window go to s_sb / s_cap.
-template <int WN, int NC>
-__device__ __forceinline__ void stage_senders(const DeviceNet &d, uint32_t j0, uint32_t nb,
-                                              uint32_t nnz, uint32_t lslot, const uint64_t *s_nzf,
-                                              const uint32_t *s_nzp, const uint16_t *s_nzb,
-                                              const WinClass *s_cls, uint64_t *s_sb,
-                                              uint32_t *s_cap) {
-  const uint32_t tid = threadIdx.x;
-  if (tid >= nb) return;
-  const uint32_t j = j0 + tid;
-  uint32_t lo = 0, hi = nnz;
-  while (hi - lo > 1) {
-    const uint32_t mid = (lo + hi) >> 1;
-    if (s_nzp[mid] <= j) lo = mid; else hi = mid;
-  }
-  const uint32_t kk = j - s_nzp[lo];
-  const uint32_t src = s_nzb[lo];
-  const uint32_t loc =
-      kk < kInline ? flag_local(s_nzf[lo], kk)
-                   : ld_ag(d.llist + size_t(lslot) * d.ntot + size_t(src) * WN + kk);
-  const uint32_t gid = src * WN + loc;
-  uint32_t cap = 0;
-  uint64_t base = 0;
-#pragma unroll
-  for (int c = 0; c < NC; ++c) {
-    const uint32_t off = gid - s_cls[c].first;
-    if (off < s_cls[c].n) {
-      cap = s_cls[c].cap;
-      base = s_cls[c].base + uint64_t(off) * cap;
+// Sender j of step t-1's set, as a global id: from the expanded list s_sid
+// (the first SB senders), else by search over the blocks with senders
+// (s_nzf / s_nzp / s_nzb, nnz of them); senders past a block's fourth come
+// from its list in memory.
+template <int WN, uint32_t SB>
+__device__ __forceinline__ uint32_t sender_gid(const DeviceNet &d, uint32_t j, uint32_t nnz,
+                                               uint32_t lslot, const uint32_t *s_sid,
+                                               const uint64_t *s_nzf, const uint32_t *s_nzp,
+                                               const uint16_t *s_nzb) {
+  uint32_t src, kk;
+  if (j < SB) {
+    const uint32_t v = s_sid[j];
+    if (!(v >> 31)) return v;
+    src = (v >> 10) & 0xFFFFu;
+    kk = v & 1023u;
+  } else {
+    uint32_t lo = 0, hi = nnz;
+    while (hi - lo > 1) {
+      const uint32_t mid = (lo + hi) >> 1;
+      if (s_nzp[mid] <= j) lo = mid; else hi = mid;
     }
+    kk = j - s_nzp[lo];
+    src = s_nzb[lo];
+    if (kk < kInline) return src * WN + flag_local(s_nzf[lo], kk);
   }
-  s_sb[tid] = base;
-  s_cap[tid] = cap;
+  return src * WN + ld_ag(d.llist + size_t(lslot) * d.ntot + size_t(src) * WN + kk);
 }
 
-// UR record slots per lane.  load() walks this wave's senders of the staged
-// batch (senders wave, wave + 4, ...; lane l holds the segment address and
-// capacity of the wave's sender l) in 64-record pieces, one piece per slot;
+// UR record slots per lane.  load() walks this wave's senders of a batch
+// (lane l holds the segment address and capacity of the wave's sender l) in
+// 64-record pieces, one piece per slot;
 // apply() adds the loaded records into rows (t_src + delay).  Unused slots
 // and empty record slots (delay 0) add nothing.
 template <bool COMP, int UR>
@@ -944,13 +935,12 @@ struct SegmentWalk {
   uint32_t cap;
   uint64_t base;
 
-  // nb must be wave-uniform.  All cursor state is scalar.
-  __device__ __forceinline__ void begin(const uint64_t *s_sb, const uint32_t *s_cap, uint32_t nb) {
-    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = __lane_id();
-    const uint32_t jl = wave + 4u * lane;
-    base_l = jl < nb ? s_sb[jl] : 0ull;
-    cap_l = jl < nb ? s_cap[jl] : 0u;
-    nl = nb > wave ? (nb - wave + 3u) / 4u : 0u;
+  // Lane l holds the segment of the wave's sender l (cap 0 past the end);
+  // n_l (wave-uniform) senders.  All cursor state is scalar.
+  __device__ __forceinline__ void begin(uint64_t base_lane, uint32_t cap_lane, uint32_t n_l) {
+    base_l = base_lane;
+    cap_l = cap_lane;
+    nl = n_l;
     l = 0;
     c0 = 0;
     pick(0);
@@ -1020,12 +1010,12 @@ __global__ __launch_bounds__(256) void k_lds(DeviceNet d, uint32_t n_steps, uint
   __shared__ int32_t s_ring[kRing * WN];
   __shared__ uint32_t s_thr[NSLOT * 8 * TS];
   __shared__ uint2 s_meta[NSLOT * 8];
-  __shared__ WinClass s_cls[NC];
+  __shared__ uint32_t s_cf[NC + 1], s_cn[NC + 1], s_ccap[NC + 1];   // sender classes
+  __shared__ uint64_t s_cbase[NC + 1];
+  __shared__ uint32_t s_sid[SB];              // senders of step t-1 (gid or list marker)
   __shared__ uint64_t s_nzf[NZ];
   __shared__ uint32_t s_nzp[NZ];
   __shared__ uint16_t s_nzb[NZ];
-  __shared__ uint64_t s_sb[SB];
-  __shared__ uint32_t s_cap[SB];
   __shared__ uint64_t s_rast[RC];
   __shared__ uint32_t s_T[NQ];                // T_t of each quad, one byte per neuron
   __shared__ uint32_t s_wave[BS / 64], s_inl[kInline];
@@ -1050,7 +1040,14 @@ __global__ __launch_bounds__(256) void k_lds(DeviceNet d, uint32_t n_steps, uint
     const uint32_t r = i / WN, c = i % WN;
     s_ring[i] = wb0 + c < d.ntot ? d.W[size_t(r) * d.ntot + wb0 + c] : 0;
   }
-  if (tid < uint32_t(NC)) s_cls[tid] = d.wcls[size_t(blk) * kWinClasses + tid];
+  if (tid <= uint32_t(NC)) {   // entry NC: no class (capacity 0)
+    WinClass c{0, 0, 0, 0, 0};
+    if (tid < uint32_t(NC)) c = d.wcls[size_t(blk) * kWinClasses + tid];
+    s_cf[tid] = c.first;
+    s_cn[tid] = c.n;
+    s_ccap[tid] = c.cap;
+    s_cbase[tid] = c.base;
+  }
   // Thalamic tables of the (256-aligned) instances in the window.
   if (tid < uint32_t(NSLOT)) {
     const uint32_t qq = wb0 / 4 + tid * 64;
@@ -1219,7 +1216,10 @@ __global__ __launch_bounds__(256) void k_lds(DeviceNet d, uint32_t n_steps, uint
       // List entries must be performed before the flag that announces them.
       if (cnt > kInline) __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
       __syncthreads();
-      if (tid == 0) {
+      // Wave 1 stores the flag: vector memory operations of a wave complete
+      // in order, so the polling wave 0 would otherwise wait for the store's
+      // acknowledgement before it can read any flag.
+      if (tid == 64) {
         uint64_t f = uint64_t(ep & 0xFFFFu) | (uint64_t(cnt) << 16);
         for (uint32_t kk = 0; kk < kInline && kk < cnt; ++kk)
           f |= uint64_t(s_inl[kk]) << (26 + 9 * kk);
@@ -1287,6 +1287,17 @@ __global__ __launch_bounds__(256) void k_lds(DeviceNet d, uint32_t n_steps, uint
           ps += c;
         }
       }
+      // The first SB senders, expanded: gid for inline ones, else a list
+      // marker (1 << 31 | block << 10 | index).
+      ps = (x - v) >> 10;
+#pragma unroll
+      for (int j = 0; j < NJ; ++j) {
+        const uint32_t c = flag_count(fv[j]);
+        const uint32_t src = rel.x + lane + 64u * uint32_t(j);
+        for (uint32_t kk = 0; kk < c && ps < SB; ++kk, ++ps)
+          s_sid[ps] = kk < kInline ? src * WN + flag_local(fv[j], kk)
+                                   : (1u << 31) | (src << 10) | kk;
+      }
       if (lane == 0) {
         s_nnz = all & 1023u;
         s_n = all >> 10;
@@ -1300,11 +1311,23 @@ __global__ __launch_bounds__(256) void k_lds(DeviceNet d, uint32_t n_steps, uint
     const uint64_t tsrc = t - 1;
     bool drawn = !decide;
     for (uint32_t j0 = 0; j0 < n_prev; j0 += SB) {
+      // This wave's senders of the batch: j0 + wave + 4 l, one per lane l.
       const uint32_t nb = min(SB, n_prev - j0);
-      stage_senders<WN, NC>(d, j0, nb, nnz, epp % kSlots, s_nzf, s_nzp, s_nzb, s_cls, s_sb, s_cap);
-      __syncthreads();
+      const uint32_t n_l = nb > wave ? (nb - wave + 3u) / 4u : 0u;
+      uint64_t base_lane = 0;
+      uint32_t cap_lane = 0;
+      if (lane < n_l) {
+        const uint32_t gid = sender_gid<WN, SB>(d, j0 + wave + 4u * lane, nnz, epp % kSlots, s_sid,
+                                                s_nzf, s_nzp, s_nzb);
+        uint32_t ci = NC;
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+          if (gid - s_cf[c] < s_cn[c]) ci = uint32_t(c);
+        cap_lane = s_ccap[ci];
+        base_lane = s_cbase[ci] + uint64_t(gid - s_cf[ci]) * cap_lane;
+      }
       SegmentWalk<COMP, UR> sw;
-      sw.begin(s_sb, s_cap, nb);
+      sw.begin(base_lane, cap_lane, n_l);
       while (sw.more()) {
         sw.load(d);
         if (!drawn) {   // T_t while the first records are in flight
@@ -1315,7 +1338,6 @@ __global__ __launch_bounds__(256) void k_lds(DeviceNet d, uint32_t n_steps, uint
         }
         sw.template apply<WN>(s_ring, tsrc, wb0);
       }
-      __syncthreads();
     }
     if (!drawn) {
       draw_thalamic(t);
