@@ -13,12 +13,12 @@ namespace snn {
 constexpr uint32_t kThrLds = 8192;
 constexpr uint32_t kMetaLds = 512;
 
-// LDS engine: neurons the whole grid can hold (one 512-neuron window per CU,
-// or two 256-neuron windows), thalamic table entries its LDS copies hold, and
-// sender classes (instance slot x population) one window can receive from.
-constexpr uint32_t kLdsNeurons = 131072;
+// LDS engine: blocks of one launch (one per CU), thalamic table entries its
+// LDS copies hold, and sender classes (the populations of the window's
+// instance) a window receives from.
+constexpr uint32_t kLdsMaxGrid = 256;
 constexpr uint32_t kLdsTab = 32;
-constexpr uint32_t kWinClasses = 16;
+constexpr uint32_t kWinClasses = 8;
 // Flag and list slots of the LDS engine: a block publishes step t only after
 // every block it reads from has published step t-2, so four slots are never
 // overwritten while a reader still needs them.
@@ -84,9 +84,12 @@ struct DeviceNet {
   DevConsts *consts = nullptr;
   Control *ctl = nullptr;
   SegEntry *seg_list = nullptr;     // persistent: [3][ntot * nwin_max]
-  uint32_t lds_window = 0;          // LDS engine: neurons per block (256 or 512), else 0
+  uint32_t lds_window = 0;          // LDS engine: window capacity of the kernel (320, 512), else 0
+  uint32_t n_lwin = 0;              // LDS engine: windows of all instances
+  const uint4 *lwin = nullptr;      // LDS engine: per window (first neuron, neurons, instance, 0)
   const WinClass *wcls = nullptr;   // LDS engine: [windows][kWinClasses]
-  const uint2 *wrel = nullptr;      // LDS engine: per window, the blocks [x, y) that reach it
+  const uint2 *wrel = nullptr;      // LDS engine: per window, the windows [x, y) of its instance
+  int64_t *blk_ctr = nullptr;       // LDS engine: [windows][4] spikes, thalamic, consumed, events
   const uint32_t *outdeg = nullptr; // LDS engine: synapses per sender [ntot]
   uint64_t *lflags = nullptr;       // LDS engine: [kSlots][windows] flag words
   uint32_t *llist = nullptr;        // LDS engine: [kSlots][ntot] senders beyond the inline ones
@@ -111,8 +114,11 @@ hipError_t launch_persistent(const DeviceNet &d, const LaunchShape &sh, uint32_t
 // quad capacity per thread it was compiled for.
 int persistent_max_grid(const DeviceNet &d, uint32_t block, uint32_t qpt);
 uint32_t persistent_qmax(uint32_t qpt);
-// LDS engine: one cooperative launch of ntot / lds_window blocks runs n steps.
-hipError_t launch_lds(const DeviceNet &d, uint32_t n, hipStream_t s);
-int lds_max_grid(uint32_t window);
+// LDS engine: one cooperative launch of windows [win0, win0 + nwin) (whole
+// instances) runs steps t0 .. t0 + n - 1; ep0 is the group's flag epoch.
+hipError_t launch_lds(const DeviceNet &d, uint32_t win0, uint32_t nwin, uint32_t n, uint64_t t0,
+                      uint32_t ep0, hipStream_t s);
+// Co-resident blocks of the LDS kernel with window capacity wn (320 or 512).
+int lds_max_grid(uint32_t wn);
 
 }  // namespace snn

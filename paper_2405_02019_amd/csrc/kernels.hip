@@ -892,19 +892,20 @@ __device__ __forceinline__ uint32_t flag_local(uint64_t f, uint32_t k) {
 }
 
 // Sender j of step t-1's set, as a global id: from the expanded list s_sid
-// (the first SB senders), else by search over the blocks with senders
-// (s_nzf / s_nzp / s_nzb, nnz of them); senders past a block's fourth come
-// from its list in memory.
-template <int WN, uint32_t SB>
+// (the first SB senders), else by search over the windows with senders
+// (s_nzf / s_nzp / s_nzb, relative to window rel0; nnz of them); senders past
+// a window's fourth come from its list in memory.
+template <uint32_t SB>
 __device__ __forceinline__ uint32_t sender_gid(const DeviceNet &d, uint32_t j, uint32_t nnz,
                                                uint32_t lslot, const uint32_t *s_sid,
                                                const uint64_t *s_nzf, const uint32_t *s_nzp,
-                                               const uint16_t *s_nzb) {
+                                               const uint16_t *s_nzb, const uint32_t *s_wstart,
+                                               uint32_t rel0) {
   uint32_t src, kk;
   if (j < SB) {
     const uint32_t v = s_sid[j];
     if (!(v >> 31)) return v;
-    src = (v >> 10) & 0xFFFFu;
+    src = (v >> 10) & 0x1FFFFFu;
     kk = v & 1023u;
   } else {
     uint32_t lo = 0, hi = nnz;
@@ -914,9 +915,10 @@ __device__ __forceinline__ uint32_t sender_gid(const DeviceNet &d, uint32_t j, u
     }
     kk = j - s_nzp[lo];
     src = s_nzb[lo];
-    if (kk < kInline) return src * WN + flag_local(s_nzf[lo], kk);
+    if (kk < kInline) return s_wstart[src] + flag_local(s_nzf[lo], kk);
   }
-  return src * WN + ld_ag(d.llist + size_t(lslot) * d.ntot + size_t(src) * WN + kk);
+  const uint32_t w0 = s_wstart[src];
+  return w0 + ld_ag(d.llist + size_t(lslot) * d.ntot + w0 + kk);
 }
 
 // UR record slots per lane.  load() walks this wave's senders of a batch
@@ -993,25 +995,25 @@ struct SegmentWalk {
 };
 
 template <int WN, bool COMP>
-__global__ __launch_bounds__(256) void k_lds(DeviceNet d, uint32_t n_steps, uint32_t spin_limit) {
+__global__ __launch_bounds__(256) void k_lds(DeviceNet d, uint32_t n_steps, uint64_t t0,
+                                             uint32_t ep0, uint32_t win0, uint32_t spin_limit) {
   constexpr uint32_t BS = 256;
-  constexpr uint32_t NQ = WN / 4;             // quads of the window
+  constexpr uint32_t NQ = WN / 4;             // quads a window can hold
   constexpr uint32_t Q0 = BS - NQ;            // threads Q0.. own one quad each
-  constexpr uint32_t NPT = WN / BS;           // neurons per thread in the thalamic draw
-  constexpr int NSLOT = WN / 256;             // instances a window can overlap
-  constexpr int NC = 8 * NSLOT;               // sender classes that can reach it
   constexpr uint32_t TS = kLdsTab + 8;        // stride of an LDS thalamic table
-  constexpr uint32_t NZ = kLdsNeurons / WN;   // largest grid of this window size
+  constexpr uint32_t NZ = kLdsMaxGrid;        // windows of one instance, at most
   constexpr int NJ = NZ / 64;                 // flags per lane of the polling wave
   constexpr uint32_t RC = WN + 128;           // raster staging entries
-  constexpr uint32_t SB = BS;                 // senders staged per batch
+  constexpr uint32_t SB = BS;                 // senders resolved per batch
   constexpr int UR = 8;                       // record pieces in flight per lane
-  static_assert(Q0 >= 64, "wave 0 polls; it owns no quad");
+  constexpr uint32_t ND = (WN + BS - 1) / BS; // neurons per thread in the thalamic draw
+  static_assert(Q0 >= 128, "waves 0 and 1 own no quad");
   __shared__ int32_t s_ring[kRing * WN];
-  __shared__ uint32_t s_thr[NSLOT * 8 * TS];
-  __shared__ uint2 s_meta[NSLOT * 8];
-  __shared__ uint32_t s_cf[NC + 1], s_cn[NC + 1], s_ccap[NC + 1];   // sender classes
-  __shared__ uint64_t s_cbase[NC + 1];
+  __shared__ uint32_t s_thr[8 * TS];
+  __shared__ uint2 s_meta[8];
+  __shared__ uint32_t s_cf[9], s_cn[9], s_ccap[9];   // sender classes; entry 8: none
+  __shared__ uint64_t s_cbase[9];
+  __shared__ uint32_t s_wstart[NZ];           // first neuron of each window of the instance
   __shared__ uint32_t s_sid[SB];              // senders of step t-1 (gid or list marker)
   __shared__ uint64_t s_nzf[NZ];
   __shared__ uint32_t s_nzp[NZ];
@@ -1019,74 +1021,59 @@ __global__ __launch_bounds__(256) void k_lds(DeviceNet d, uint32_t n_steps, uint
   __shared__ uint64_t s_rast[RC];
   __shared__ uint32_t s_T[NQ];                // T_t of each quad, one byte per neuron
   __shared__ uint32_t s_wave[BS / 64], s_inl[kInline];
-  __shared__ uint32_t s_inst[NSLOT], s_flag, s_n, s_nnz;
+  __shared__ uint32_t s_flag, s_n, s_nnz;
   __shared__ unsigned long long s_rbase;
+  __shared__ long long s_ctr[4];
 
-  const uint32_t G = gridDim.x, blk = blockIdx.x;
+  const uint32_t GT = d.n_lwin, blk = win0 + blockIdx.x;
   const uint32_t tid = threadIdx.x, lane = __lane_id();
   const uint32_t wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const uint32_t wb0 = blk * WN;
-  const uint32_t oq = tid - Q0;                              // owned quad in the window
+  const uint4 wi = d.lwin[blk];               // (first neuron, neurons, instance, -)
+  const uint32_t wb0 = wi.x, wlen = wi.y, inst = wi.z;
+  const uint32_t oq = tid - Q0;               // owned quad in the window
   const uint32_t q = wb0 / 4 + oq;
-  const bool owner = tid >= Q0 && q < d.nquads;
-  const uint64_t t0 = d.ctl->t_base;
-  const uint32_t ep0 = d.ctl->epoch;
+  const bool owner = tid >= Q0 && oq < wlen / 4;
+  const InstDev *ip = d.inst + inst;
   const Props k{d.consts->p11, d.consts->p22, d.consts->p21};
-  const uint2 rel = d.wrel[blk];   // blocks whose senders can reach this window
+  const uint2 rel = d.wrel[blk];              // windows whose senders can reach this one
   uint64_t *const flags = d.lflags;
 
   // Ring rows of the window into LDS.
   for (uint32_t i = tid; i < kRing * WN; i += BS) {
     const uint32_t r = i / WN, c = i % WN;
-    s_ring[i] = wb0 + c < d.ntot ? d.W[size_t(r) * d.ntot + wb0 + c] : 0;
+    s_ring[i] = c < wlen ? d.W[size_t(r) * d.ntot + wb0 + c] : 0;
   }
-  if (tid <= uint32_t(NC)) {   // entry NC: no class (capacity 0)
+  if (tid <= 8u) {   // entry 8: no class (capacity 0)
     WinClass c{0, 0, 0, 0, 0};
-    if (tid < uint32_t(NC)) c = d.wcls[size_t(blk) * kWinClasses + tid];
+    if (tid < 8u) c = d.wcls[size_t(blk) * kWinClasses + tid];
     s_cf[tid] = c.first;
     s_cn[tid] = c.n;
     s_ccap[tid] = c.cap;
     s_cbase[tid] = c.base;
   }
-  // Thalamic tables of the (256-aligned) instances in the window.
-  if (tid < uint32_t(NSLOT)) {
-    const uint32_t qq = wb0 / 4 + tid * 64;
-    s_inst[tid] = qq < d.nquads ? d.qinfo[qq] >> 24 : 0xFFFFFFFFu;
-  }
-  __syncthreads();
-  if (tid < uint32_t(NSLOT * 8)) {
-    const uint32_t slot = tid >> 3, p = tid & 7u;
-    const uint32_t inst = s_inst[slot];
-    uint2 m = make_uint2(0, 0);
-    if (inst != 0xFFFFFFFFu) m = d.pmeta[inst * 8 + p];
-    const uint32_t off = (slot * 8 + p) * TS;
+  if (tid < 4u) s_ctr[tid] = 0;
+  for (uint32_t i = tid; i < rel.y - rel.x; i += BS) s_wstart[i] = d.lwin[rel.x + i].x;
+  // Thalamic tables of the window's instance.
+  if (tid < 8u) {
+    const uint2 m = d.pmeta[inst * 8 + tid];
+    const uint32_t off = tid * TS;
     for (uint32_t kk = 0; kk < TS; ++kk)
       s_thr[off + kk] = kk < m.y ? d.thr[m.x + kk] : 0xFFFFFFFFu;
-    s_meta[slot * 8 + p] = make_uint2(off, m.y);
+    s_meta[tid] = make_uint2(off, m.y);
   }
 
-  // Thalamic draw: thread tid handles neurons NPT tid .. NPT tid + NPT - 1 of
-  // the window (one quad's Philox block); tmeta = s_meta index or 0xFF.
-  uint32_t d_lq = 0, tmeta = 0xFFFFFFFFu;
-  uint64_t d_seed = 0;
-  {
-    const uint32_t n0 = wb0 + NPT * tid;
-    const uint32_t dq = n0 / 4;
-    if (dq < d.nquads) {
-      const uint32_t qi = d.qinfo[dq];
-      const InstDev *ip = d.inst + (qi >> 24);
-      d_lq = qi & 0xFFFFFFu;
-      d_seed = ip->seed;
-      const uint32_t code = quad_code(ip, d_lq);
-      const uint32_t sl = NSLOT > 1 && (qi >> 24) != s_inst[0] ? 1u : 0u;
-      tmeta = 0;
+  // Thalamic draw: thread tid handles window neurons tid + BS i (i < ND);
+  // tmeta byte i = population of that neuron, 0xFF when it is padding.
+  uint32_t tmeta = 0xFFFFFFFFu;
 #pragma unroll
-      for (uint32_t i = 0; i < NPT; ++i) {
-        const uint32_t m = (n0 + i) & 3u;
-        const uint32_t v = ((code >> (12 + m)) & 1u) ? sl * 8u + ((code >> (3 * m)) & 7u) : 0xFFu;
-        tmeta |= v << (8 * i);
-      }
+  for (uint32_t i = 0; i < ND; ++i) {
+    const uint32_t c = tid + BS * i;
+    uint32_t v = 0xFFu;
+    if (c < wlen) {
+      const uint32_t local = wb0 + c - ip->gbase;
+      if (local < ip->n) v = population(ip, local);
     }
+    tmeta = (tmeta & ~(0xFFu << (8 * i))) | (v << (8 * i));
   }
 
   float U[4] = {0, 0, 0, 0}, I[4] = {0, 0, 0, 0};
@@ -1094,20 +1081,18 @@ __global__ __launch_bounds__(256) void k_lds(DeviceNet d, uint32_t n_steps, uint
   uint32_t OD[4] = {0, 0, 0, 0};
   int64_t c_con = 0;
   uint64_t c_ev = 0;
-  int32_t wext = 0;
+  const int32_t wext = ip->w_ext_q;
   if (owner) {
     const float4 uv = ld4(d.U + 4 * size_t(q));
     const float4 iv = ld4(d.I + 4 * size_t(q));
     U[0] = uv.x; U[1] = uv.y; U[2] = uv.z; U[3] = uv.w;
     I[0] = iv.x; I[1] = iv.y; I[2] = iv.z; I[3] = iv.w;
     R = d.R4[q];
-    const uint32_t qi = d.qinfo[q];
-    const InstDev *ip = d.inst + (qi >> 24);
-    PC = quad_code(ip, qi & 0xFFFFFFu);
-    wext = ip->w_ext_q;
+    PC = quad_code(ip, q - ip->gbase / 4);
     const uint4 od = *reinterpret_cast<const uint4 *>(d.outdeg + 4 * size_t(q));
     OD[0] = od.x; OD[1] = od.y; OD[2] = od.z; OD[3] = od.w;
   }
+  const uint64_t seed = ip->seed;
   __syncthreads();
 
   // Flushes the staged raster entries to the device raster.
@@ -1128,24 +1113,25 @@ __global__ __launch_bounds__(256) void k_lds(DeviceNet d, uint32_t n_steps, uint
     rn = 0;
   };
 
-  // Thalamic counts T_t of this thread's neurons into s_T (byte per neuron).
+  // Thalamic counts T_t of this thread's neurons into s_T (byte per neuron);
+  // one Philox block per quad (eqn:ref's background drive, Sec. 2.2).
+  uint32_t lq_base = (wb0 - ip->gbase) / 4;
   auto draw_thalamic = [&](uint64_t t) {
-    if (tmeta == 0xFFFFFFFFu) return;
-    const Philox4 x = philox4x32_10(d_lq, uint32_t(t), uint32_t(t >> 32), kStreamThalamic,
-                                    uint32_t(d_seed), uint32_t(d_seed >> 32));
-    uint32_t packed = 0;
 #pragma unroll
-    for (uint32_t i = 0; i < NPT; ++i) {
+    for (uint32_t i = 0; i < ND; ++i) {
       const uint32_t mi = (tmeta >> (8 * i)) & 0xFFu;
-      const uint32_t m = (NPT * tid + i) & 3u;
-      const uint32_t u = m == 0 ? x.v[0] : m == 1 ? x.v[1] : m == 2 ? x.v[2] : x.v[3];
-      const uint32_t T = mi == 0xFFu ? 0u : thalamic_count(s_thr, s_meta[mi], u);
-      packed |= T << (8 * i);
+      const uint32_t c = tid + BS * i;
+      if (c >= wlen) continue;
+      uint32_t T = 0;
+      if (mi != 0xFFu) {
+        const Philox4 x = philox4x32_10(lq_base + c / 4, uint32_t(t), uint32_t(t >> 32),
+                                        kStreamThalamic, uint32_t(seed), uint32_t(seed >> 32));
+        const uint32_t m = c & 3u;
+        const uint32_t u = m == 0 ? x.v[0] : m == 1 ? x.v[1] : m == 2 ? x.v[2] : x.v[3];
+        T = thalamic_count(s_thr, s_meta[mi], u);
+      }
+      reinterpret_cast<uint8_t *>(s_T)[c] = uint8_t(T);
     }
-    if (NPT == 1)
-      reinterpret_cast<uint8_t *>(s_T)[tid] = uint8_t(packed);
-    else
-      reinterpret_cast<uint16_t *>(s_T)[tid] = uint16_t(packed);
   };
 
   for (uint32_t it = 0; it <= n_steps; ++it) {
@@ -1153,7 +1139,7 @@ __global__ __launch_bounds__(256) void k_lds(DeviceNet d, uint32_t n_steps, uint
     const bool decide = it < n_steps;
     const uint32_t ep = ep0 + it + 1;         // epoch of step t's flags
     const uint32_t epp = ep - 1;              // epoch of step t-1's flags
-    const uint64_t *fs = flags + size_t(epp % kSlots) * G;
+    const uint64_t *fs = flags + size_t(epp % kSlots) * GT;
 
     // Wave 0 issues the flag loads of step t-1 now; they are checked in (c).
     uint64_t fv[NJ];
@@ -1223,7 +1209,7 @@ __global__ __launch_bounds__(256) void k_lds(DeviceNet d, uint32_t n_steps, uint
         uint64_t f = uint64_t(ep & 0xFFFFu) | (uint64_t(cnt) << 16);
         for (uint32_t kk = 0; kk < kInline && kk < cnt; ++kk)
           f |= uint64_t(s_inl[kk]) << (26 + 9 * kk);
-        st_ag(flags + size_t(ep % kSlots) * G + blk, f);
+        st_ag(flags + size_t(ep % kSlots) * GT + blk, f);
       }
       rn += cnt;
       if (rn > RC - WN) flush();
@@ -1235,7 +1221,7 @@ __global__ __launch_bounds__(256) void k_lds(DeviceNet d, uint32_t n_steps, uint
       continue;
     }
 
-    // (c) wait for step t-1's flags; collect the blocks that have senders.
+    // (c) wait for step t-1's flags; collect the windows that have senders.
     if (wave == 0) {
       uint32_t spins = 0;
       bool ok = true;
@@ -1266,7 +1252,7 @@ __global__ __launch_bounds__(256) void k_lds(DeviceNet d, uint32_t n_steps, uint
         nzc += c ? 1u : 0u;
         sc += c;
       }
-      // inclusive wave scan of (senders << 10 | blocks with senders)
+      // inclusive wave scan of (senders << 10 | windows with senders)
       const uint32_t v = (sc << 10) | nzc;
       uint32_t x = v;
 #pragma unroll
@@ -1282,20 +1268,20 @@ __global__ __launch_bounds__(256) void k_lds(DeviceNet d, uint32_t n_steps, uint
         if (c) {
           s_nzf[pz] = fv[j];
           s_nzp[pz] = ps;
-          s_nzb[pz] = uint16_t(rel.x + lane + 64u * uint32_t(j));
+          s_nzb[pz] = uint16_t(lane + 64u * uint32_t(j));   // window, relative to rel.x
           ++pz;
           ps += c;
         }
       }
       // The first SB senders, expanded: gid for inline ones, else a list
-      // marker (1 << 31 | block << 10 | index).
+      // marker (1 << 31 | relative window << 10 | index).
       ps = (x - v) >> 10;
 #pragma unroll
       for (int j = 0; j < NJ; ++j) {
         const uint32_t c = flag_count(fv[j]);
-        const uint32_t src = rel.x + lane + 64u * uint32_t(j);
+        const uint32_t src = lane + 64u * uint32_t(j);
         for (uint32_t kk = 0; kk < c && ps < SB; ++kk, ++ps)
-          s_sid[ps] = kk < kInline ? src * WN + flag_local(fv[j], kk)
+          s_sid[ps] = kk < kInline ? s_wstart[src] + flag_local(fv[j], kk)
                                    : (1u << 31) | (src << 10) | kk;
       }
       if (lane == 0) {
@@ -1317,11 +1303,11 @@ __global__ __launch_bounds__(256) void k_lds(DeviceNet d, uint32_t n_steps, uint
       uint64_t base_lane = 0;
       uint32_t cap_lane = 0;
       if (lane < n_l) {
-        const uint32_t gid = sender_gid<WN, SB>(d, j0 + wave + 4u * lane, nnz, epp % kSlots, s_sid,
-                                                s_nzf, s_nzp, s_nzb);
-        uint32_t ci = NC;
+        const uint32_t gid = sender_gid<SB>(d, j0 + wave + 4u * lane, nnz, epp % kSlots, s_sid,
+                                            s_nzf, s_nzp, s_nzb, s_wstart, rel.x);
+        uint32_t ci = 8;
 #pragma unroll
-        for (int c = 0; c < NC; ++c)
+        for (int c = 0; c < 8; ++c)
           if (gid - s_cf[c] < s_cn[c]) ci = uint32_t(c);
         cap_lane = s_ccap[ci];
         base_lane = s_cbase[ci] + uint64_t(gid - s_cf[ci]) * cap_lane;
@@ -1332,7 +1318,7 @@ __global__ __launch_bounds__(256) void k_lds(DeviceNet d, uint32_t n_steps, uint
         sw.load(d);
         if (!drawn) {   // T_t while the first records are in flight
           // Keeps the draw from being scheduled ahead of the loads.
-          asm volatile("" : "+v"(d_lq) : : "memory");
+          asm volatile("" : "+v"(lq_base) : : "memory");
           draw_thalamic(t);
           drawn = true;
         }
@@ -1351,7 +1337,7 @@ __global__ __launch_bounds__(256) void k_lds(DeviceNet d, uint32_t n_steps, uint
   if (rn) flush();
   for (uint32_t i = tid; i < kRing * WN; i += BS) {
     const uint32_t r = i / WN, c = i % WN;
-    if (wb0 + c < d.ntot) d.W[size_t(r) * d.ntot + wb0 + c] = s_ring[i];
+    if (c < wlen) d.W[size_t(r) * d.ntot + wb0 + c] = s_ring[i];
   }
   if (owner) {
     *reinterpret_cast<float4 *>(d.U + 4 * size_t(q)) = make_float4(U[0], U[1], U[2], U[3]);
@@ -1368,37 +1354,27 @@ __global__ __launch_bounds__(256) void k_lds(DeviceNet d, uint32_t n_steps, uint
       ev += __shfl_xor(ev, o);
       co += __shfl_xor(co, o);
     }
-    if (lane == 0 && tid >= Q0 && q < d.nquads) {
-      int64_t *c = d.wave_ctr + 4 * size_t(q >> 6);
-      c[0] += int64_t(sp);
-      c[1] += int64_t(po);
-      c[2] += co;
-      c[3] += int64_t(ev);
+    if (lane == 0 && wave >= Q0 / 64) {
+      atomicAdd(reinterpret_cast<unsigned long long *>(&s_ctr[0]), (unsigned long long)sp);
+      atomicAdd(reinterpret_cast<unsigned long long *>(&s_ctr[1]), (unsigned long long)po);
+      atomicAdd(reinterpret_cast<unsigned long long *>(&s_ctr[2]), (unsigned long long)co);
+      atomicAdd(reinterpret_cast<unsigned long long *>(&s_ctr[3]), (unsigned long long)ev);
     }
   }
-  __builtin_amdgcn_s_waitcnt(0x0F70);
   __syncthreads();
-  if (tid == 0) {
-    const uint64_t done =
-        __hip_atomic_fetch_add(&d.ctl->exit_count, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (done == G - 1) {
-      st_ag(&d.ctl->exit_count, 0ull);
-      st_ag(&d.ctl->epoch, ep0 + n_steps);
-      st_ag(&d.ctl->t_base, t0 + n_steps);
-    }
-  }
+  if (tid < 4u) d.blk_ctr[size_t(blk) * 4 + tid] += s_ctr[tid];
 }
 
-using LdsFn = void (*)(DeviceNet, uint32_t, uint32_t);
+using LdsFn = void (*)(DeviceNet, uint32_t, uint64_t, uint32_t, uint32_t, uint32_t);
 
-static LdsFn lds_fn(uint32_t window, bool comp) {
-  if (window == 512) return comp ? k_lds<512, true> : k_lds<512, false>;
-  if (window == 256) return comp ? k_lds<256, true> : k_lds<256, false>;
+static LdsFn lds_fn(uint32_t wn, bool comp) {
+  if (wn == 512) return comp ? k_lds<512, true> : k_lds<512, false>;
+  if (wn == 320) return comp ? k_lds<320, true> : k_lds<320, false>;
   return nullptr;
 }
 
-int lds_max_grid(uint32_t window) {
-  LdsFn fn = lds_fn(window, false);
+int lds_max_grid(uint32_t wn) {
+  LdsFn fn = lds_fn(wn, false);
   if (!fn) return 0;
   int per_cu = 0, dev = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(fn), 256,
@@ -1406,19 +1382,20 @@ int lds_max_grid(uint32_t window) {
     return 0;
   hipDeviceProp_t prop;
   if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return 0;
-  return std::min<int>(per_cu * prop.multiProcessorCount, int(kLdsNeurons / window));
+  return std::min<int>(std::min(per_cu, 1) * prop.multiProcessorCount, int(kLdsMaxGrid));
 }
 
-hipError_t launch_lds(const DeviceNet &d, uint32_t n, hipStream_t s) {
+hipError_t launch_lds(const DeviceNet &d, uint32_t win0, uint32_t nwin, uint32_t n, uint64_t t0,
+                      uint32_t ep0, hipStream_t s) {
   LdsFn fn = lds_fn(d.lds_window, d.syn_format == SNN_SYN_COMPRESSED5);
-  if (!fn) return hipErrorInvalidConfiguration;
-  const uint32_t grid = (d.ntot + d.lds_window - 1) / d.lds_window;
-  if (grid > kLdsNeurons / d.lds_window) return hipErrorInvalidConfiguration;
+  if (!fn || nwin == 0 || nwin > kLdsMaxGrid || win0 + nwin > d.n_lwin)
+    return hipErrorInvalidConfiguration;
   DeviceNet dv = d;
-  uint32_t steps = n;
+  uint32_t steps = n, e0 = ep0, w0 = win0;
+  uint64_t tt = t0;
   uint32_t spin = 1u << 24;
-  void *args[] = {&dv, &steps, &spin};
-  return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(fn), dim3(grid), dim3(256), args,
+  void *args[] = {&dv, &steps, &tt, &e0, &w0, &spin};
+  return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(fn), dim3(nwin), dim3(256), args,
                                     0, s);
 }
 

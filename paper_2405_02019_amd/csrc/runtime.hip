@@ -19,6 +19,7 @@ thread_local std::string g_build_error;
 
 struct InstMeta {
   uint32_t n = 0, gbase = 0, npad = 0;
+  uint32_t win0 = 0, nwin = 0, wlen = 0;   // LDS engine: windows and their length (neurons)
   uint32_t pop_off[9] = {};
   uint64_t nsyn = 0;
   double w_f = 0.0;
@@ -45,6 +46,8 @@ struct snn_net {
   uint64_t pending = 0;             // worst-case raster entries since the last drain
   bool overflowed = false;
   bool dead = false;
+  std::vector<uint2> lds_groups;    // LDS engine: launches (first window, windows)
+  std::vector<uint32_t> lds_epoch;  // LDS engine: flag epoch of each group
   std::string err;
   double build_seconds = 0.0;
 };
@@ -137,23 +140,82 @@ uint64_t spike_bound(const snn_net *h, uint64_t steps) {
   return h->n_real * ((steps + kRefSteps) / (kRefSteps + 1));
 }
 
-// LDS engine: block b owns neurons [b W, (b+1) W) with their 64 ring rows in
-// LDS.  W = 256 (two blocks per CU: more blocks share the delivery work) when
-// the network fits, else W = 512; a requested grid size selects the window
-// that gives it.  0 when neither fits the co-resident grid.
-uint32_t lds_capacity() {
-  const int g512 = lds_max_grid(512), g256 = lds_max_grid(256);
-  return uint32_t(std::max(int64_t(g512) * 512, int64_t(g256) * 256));
+// LDS engine plan.  Instance k's nq quads are cut into nwin windows of at
+// most L neurons (balanced: every window has ceil(nq / nwin) quads but the
+// last); a block owns one window and its 64 ring rows in LDS.  Windows are
+// numbered instance by instance, and consecutive instances are launched
+// together while their windows fit the co-resident grid (one block per CU).
+// Automatic choice: the shortest window (at least 256 neurons) that puts the
+// whole network into one launch, else 512-neuron windows in several
+// launches.  A requested grid size fixes the number of windows.
+struct LdsPlan {
+  uint32_t wn = 0;   // kernel window capacity: 320 or 512
+  uint32_t total = 0;
+  std::vector<uint32_t> nwin, wq;
+  std::vector<uint2> groups;
+};
+
+uint32_t quads_of(const InstMeta &m) { return (m.n + 3) / 4; }
+
+uint32_t windows_for(uint32_t nq, uint32_t L) { return (nq + L / 4 - 1) / (L / 4); }
+
+bool make_plan(const std::vector<InstMeta> &im, uint32_t L, uint32_t wn, uint32_t maxg,
+               LdsPlan &p) {
+  p = LdsPlan();
+  p.wn = wn;
+  uint32_t g0 = 0, gsize = 0;
+  for (const InstMeta &m : im) {
+    const uint32_t nq = quads_of(m);
+    const uint32_t nw0 = windows_for(nq, L);
+    if (nw0 == 0) return false;
+    const uint32_t wq = (nq + nw0 - 1) / nw0;
+    const uint32_t nw = (nq + wq - 1) / wq;   // can be below nw0 after balancing
+    if (nw > maxg || 4 * wq > wn) return false;
+    p.nwin.push_back(nw);
+    p.wq.push_back(wq);
+    if (gsize + nw > maxg) {
+      p.groups.push_back(make_uint2(g0, gsize));
+      g0 += gsize;
+      gsize = 0;
+    }
+    gsize += nw;
+    p.total += nw;
+  }
+  p.groups.push_back(make_uint2(g0, gsize));
+  return true;
 }
 
-uint32_t choose_lds_window(uint32_t ntot, uint32_t block, uint32_t grid) {
-  if (block && block != 256) return 0;
-  for (uint32_t w : {256u, 512u}) {
-    const uint32_t g = (ntot + w - 1) / w;
-    if (grid && grid != g) continue;
-    if (int64_t(g) <= int64_t(lds_max_grid(w))) return w;
+int plan_lds(const std::vector<InstMeta> &im, uint32_t block, uint32_t grid, LdsPlan &p,
+             std::string &why) {
+  if (block && block != 256) {
+    why = "the LDS engine runs 256-thread blocks";
+    return SNN_E_INVAL;
   }
-  return 0;
+  const int g320 = lds_max_grid(320), g512 = lds_max_grid(512);
+  if (g320 <= 0 || g512 <= 0) {
+    why = "the LDS kernel cannot be made co-resident on this device";
+    return SNN_E_RANGE;
+  }
+  if (grid) {   // exactly `grid` windows in one launch
+    for (uint32_t L = 512; L >= 4; L -= 4) {
+      const uint32_t wn = L <= 320 ? 320 : 512;
+      const uint32_t maxg = uint32_t(wn == 320 ? g320 : g512);
+      if (make_plan(im, L, wn, maxg, p) && p.groups.size() == 1 && p.total == grid) return SNN_OK;
+    }
+    why = "no window length gives the requested number of blocks in one launch";
+    return SNN_E_RANGE;
+  }
+  uint64_t nq = 0;
+  for (const InstMeta &m : im) nq += quads_of(m);
+  for (uint32_t L = 256; L <= 512; L += 4) {
+    const uint32_t wn = L <= 320 ? 320 : 512;
+    const uint32_t maxg = uint32_t(wn == 320 ? g320 : g512);
+    if (4 * nq > uint64_t(maxg) * L) continue;
+    if (make_plan(im, L, wn, maxg, p) && p.groups.size() == 1) return SNN_OK;
+  }
+  if (make_plan(im, 512, 512, uint32_t(g512), p)) return SNN_OK;
+  why = "an instance needs more windows than the LDS engine can keep co-resident";
+  return SNN_E_RANGE;
 }
 
 // Persistent grid: 4 neurons per quad, `qpt` quads per thread, at most the
@@ -182,7 +244,11 @@ int choose_persistent_shape(snn_net *h, uint32_t block, uint32_t grid) {
 
 int queue_steps(snn_net *h, uint32_t n) {
   if (h->engine == SNN_ENGINE_LDS) {
-    HIP_OK(h, launch_lds(h->d, n, h->stream));
+    for (size_t g = 0; g < h->lds_groups.size(); ++g) {
+      const uint2 gr = h->lds_groups[g];
+      HIP_OK(h, launch_lds(h->d, gr.x, gr.y, n, h->t, h->lds_epoch[g], h->stream));
+      h->lds_epoch[g] += n;
+    }
     return SNN_OK;
   }
   if (h->engine == SNN_ENGINE_PERSISTENT) {
@@ -288,19 +354,35 @@ int snn_build(const snn_config *cfg, snn_net **out) {
   // aggregate LDS (one 512- or 256-neuron window per co-resident block) ----
   h->engine = cfg->engine == SNN_ENGINE_AUTO ? SNN_ENGINE_LDS : cfg->engine;
   uint32_t lds_window = 0;
+  LdsPlan plan;
   if (h->engine == SNN_ENGINE_LDS) {
     uint32_t tab = 0;
     for (uint32_t k = 0; k < ni; ++k) tab = std::max(tab, thalamic_table_max(cfg->inst[k]));
-    lds_window = tab <= kLdsTab ? choose_lds_window(ntot, cfg->block_size, cfg->grid_blocks) : 0;
-    if (!lds_window) {
+    std::string why;
+    int prc = SNN_E_RANGE;
+    if (tab > kLdsTab) {
+      char b[128];
+      std::snprintf(b, sizeof b, "the LDS engine holds thalamic tables of at most %u entries (need %u)",
+                    kLdsTab, tab);
+      why = b;
+    } else {
+      prc = plan_lds(h->im, cfg->block_size, cfg->grid_blocks, plan, why);
+    }
+    if (prc == SNN_OK) {
+      lds_window = plan.wn;
+      uint32_t w0 = 0;
+      for (uint32_t k = 0; k < ni; ++k) {
+        h->im[k].win0 = w0;
+        h->im[k].nwin = plan.nwin[k];
+        h->im[k].wlen = 4 * plan.wq[k];
+        w0 += plan.nwin[k];
+      }
+      h->lds_groups = plan.groups;
+      h->lds_epoch.assign(plan.groups.size(), 0);
+    } else {
       if (cfg->engine == SNN_ENGINE_LDS) {
-        if (tab > kLdsTab)
-          fail(h, SNN_E_RANGE, "the LDS engine holds thalamic tables of at most %u entries (need %u)",
-               kLdsTab, tab);
-        else
-          fail(h, SNN_E_RANGE, "the LDS engine holds at most %u neurons on this device",
-               lds_capacity());
-        return bail(SNN_E_RANGE);
+        fail(h, prc, "%s", why.c_str());
+        return bail(prc);
       }
       h->engine = SNN_ENGINE_PERSISTENT;
     }
@@ -314,8 +396,7 @@ int snn_build(const snn_config *cfg, snn_net **out) {
     InstMeta &m = h->im[k];
     uint32_t wsize = kNoWindows, worigin = 0;
     if (lds_window) {
-      wsize = lds_window;
-      worigin = m.gbase;
+      wsize = m.wlen;
     } else if (cfg->syn_format == SNN_SYN_COMPRESSED5) {
       wsize = 1u << kTargetBlockBits;
     }
@@ -325,6 +406,10 @@ int snn_build(const snn_config *cfg, snn_net **out) {
     if (rc) {
       fail(h, rc, "instance %u: %s", k, e.c_str());
       return bail(rc);
+    }
+    if (lds_window && hi[k].nwin != m.nwin) {
+      fail(h, SNN_E_RANGE, "instance %u: %u windows sampled, %u planned", k, hi[k].nwin, m.nwin);
+      return bail(SNN_E_RANGE);
     }
     std::memcpy(m.pop_off, hi[k].pop_off, sizeof m.pop_off);
     m.nsyn = hi[k].nsyn;
@@ -341,6 +426,7 @@ int snn_build(const snn_config *cfg, snn_net **out) {
   d.ntot = ntot;
   d.nquads = ntot / 4;
   d.lds_window = lds_window;
+  d.n_lwin = plan.total;
   d.nwin_max = nwin_max;
   d.syn_format = cfg->syn_format;
 
@@ -400,16 +486,19 @@ int snn_build(const snn_config *cfg, snn_net **out) {
   ALLOC(d.consts, 1);
   ALLOC(d.ctl, 1);
   if (h->engine == SNN_ENGINE_PERSISTENT) ALLOC(d.seg_list, 3 * size_t(d.ntot) * nwin_max);
-  const uint32_t nwin_lds = lds_window ? (d.ntot + lds_window - 1) / lds_window : 0;
+  const uint32_t nwin_lds = lds_window ? plan.total : 0;
   WinClass *d_wcls = nullptr;
   uint2 *d_wrel = nullptr;
+  uint4 *d_lwin = nullptr;
   uint32_t *d_outdeg = nullptr;
   if (lds_window) {
     ALLOC(d_wcls, size_t(nwin_lds) * kWinClasses);
     ALLOC(d_wrel, nwin_lds);
+    ALLOC(d_lwin, nwin_lds);
     ALLOC(d_outdeg, d.ntot);
     ALLOC(d.lflags, kSlots * size_t(nwin_lds));
     ALLOC(d.llist, kSlots * size_t(d.ntot));
+    ALLOC(d.blk_ctr, 4 * size_t(nwin_lds));
   }
 #undef ALLOC
 
@@ -472,41 +561,36 @@ int snn_build(const snn_config *cfg, snn_net **out) {
   UPLOAD(d.U, u0.data(), u0.size() * sizeof(float));
   UPLOAD(d_seg, seg.data(), seg.size() * sizeof(uint64_t));
   if (lds_window) {
-    // Per target window: the sender classes of the (at most two) instances it
-    // overlaps, and the block range of those instances.
+    // Per window: its neurons, the sender classes of its instance, and the
+    // windows of that instance (the only ones whose senders reach it).
     std::vector<WinClass> wcls(size_t(nwin_lds) * kWinClasses);
-    std::vector<uint2> wrel(nwin_lds, make_uint2(0xFFFFFFFFu, 0u));
-    std::vector<uint32_t> used(nwin_lds, 0), outdeg(d.ntot, 0);
-    const uint32_t slots = lds_window / kInstAlign;
+    std::vector<uint2> wrel(nwin_lds);
+    std::vector<uint4> lwin(nwin_lds);
+    std::vector<uint32_t> outdeg(d.ntot, 0);
     uint64_t rb = 0;
     for (uint32_t k = 0; k < ni; ++k) {
       const HostInstance &x = hi[k];
       const InstMeta &m = h->im[k];
-      for (uint32_t w = 0; w < x.nwin; ++w) {
-        const uint32_t gw = x.win_first + w;
-        if (gw >= nwin_lds || used[gw] >= slots) {
-          fail(h, SNN_E_RANGE, "window %u overlaps more than %u instances", gw, slots);
-          return bail(SNN_E_RANGE);
-        }
-        const uint32_t sl = used[gw]++;
+      const uint32_t span = 4 * quads_of(m);
+      for (uint32_t w = 0; w < m.nwin; ++w) {
+        const uint32_t gw = m.win0 + w;
+        const uint32_t first = w * m.wlen;
+        lwin[gw] = make_uint4(m.gbase + first, std::min(m.wlen, span - first), k, 0);
+        wrel[gw] = make_uint2(m.win0, m.win0 + m.nwin);
         for (int c = 0; c < 8; ++c) {
-          WinClass &e = wcls[size_t(gw) * kWinClasses + sl * 8 + c];
+          WinClass &e = wcls[size_t(gw) * kWinClasses + c];
           e.base = rb + x.cls_base[size_t(w) * 8 + c];
           e.first = m.gbase + x.pop_off[c];
           e.n = x.pop_off[c + 1] - x.pop_off[c];
           e.cap = x.cls_cap[size_t(w) * 8 + c];
         }
       }
-      for (uint32_t w = 0; w < x.nwin; ++w) {
-        uint2 &r = wrel[x.win_first + w];
-        r.x = std::min(r.x, x.win_first);
-        r.y = std::max(r.y, x.win_first + x.nwin);
-      }
       std::copy(x.outdeg.begin(), x.outdeg.end(), outdeg.begin() + m.gbase);
       rb += x.nrec;
     }
     UPLOAD(d_wcls, wcls.data(), wcls.size() * sizeof(WinClass));
     UPLOAD(d_wrel, wrel.data(), wrel.size() * sizeof(uint2));
+    UPLOAD(d_lwin, lwin.data(), lwin.size() * sizeof(uint4));
     UPLOAD(d_outdeg, outdeg.data(), outdeg.size() * sizeof(uint32_t));
   }
   syn_base = 0;
@@ -543,6 +627,7 @@ int snn_build(const snn_config *cfg, snn_net **out) {
   d.d8 = d_d8;
   d.wcls = d_wcls;
   d.wrel = d_wrel;
+  d.lwin = d_lwin;
   d.outdeg = d_outdeg;
   if (hipMemset(d.I, 0, d.ntot * sizeof(float)) != hipSuccess ||
       hipMemset(d.R4, 0, d.nquads * sizeof(uint32_t)) != hipSuccess ||
@@ -551,7 +636,8 @@ int snn_build(const snn_config *cfg, snn_net **out) {
       hipMemset(d.wave_ctr, 0, 4 * size_t(d.nquads / 64) * sizeof(int64_t)) != hipSuccess ||
       hipMemset(d.events, 0, ni * sizeof(uint64_t)) != hipSuccess ||
       hipMemset(d.ctl, 0, sizeof(Control)) != hipSuccess ||
-      (d.lflags && hipMemset(d.lflags, 0, kSlots * size_t(nwin_lds) * sizeof(uint64_t)) != hipSuccess)) {
+      (d.lflags && hipMemset(d.lflags, 0, kSlots * size_t(nwin_lds) * sizeof(uint64_t)) != hipSuccess) ||
+      (d.blk_ctr && hipMemset(d.blk_ctr, 0, 4 * size_t(nwin_lds) * sizeof(int64_t)) != hipSuccess)) {
     fail(h, SNN_E_HIP, "device memset failed");
     return bail(SNN_E_HIP);
   }
@@ -566,7 +652,7 @@ int snn_build(const snn_config *cfg, snn_net **out) {
   h->shape.scatter_blocks = 1024;
   if (h->engine == SNN_ENGINE_LDS) {
     h->shape.block = 256;
-    h->shape.grid = (d.ntot + lds_window - 1) / lds_window;
+    h->shape.grid = plan.total;
     h->shape.qpt = 1;
   } else if (h->engine == SNN_ENGINE_PERSISTENT) {
     int rc2 = choose_persistent_shape(h, cfg->block_size, cfg->grid_blocks);
@@ -680,6 +766,17 @@ int snn_read_state(snn_net *h, uint32_t inst, snn_state *out) {
     po += wc[4 * w + 1];
     co += wc[4 * w + 2];
     ev_slots += wc[4 * w + 3];
+  }
+  if (d.blk_ctr && m.nwin) {   // LDS engine: one counter set per window
+    std::vector<int64_t> bc(4 * size_t(m.nwin));
+    HIP_OK(h, hipMemcpy(bc.data(), d.blk_ctr + 4 * size_t(m.win0), bc.size() * sizeof(int64_t),
+                        hipMemcpyDeviceToHost));
+    for (size_t w = 0; w < m.nwin; ++w) {
+      sp += bc[4 * w];
+      po += bc[4 * w + 1];
+      co += bc[4 * w + 2];
+      ev_slots += bc[4 * w + 3];
+    }
   }
   uint64_t ev = 0;
   HIP_OK(h, hipMemcpy(&ev, d.events + inst, sizeof ev, hipMemcpyDeviceToHost));
