@@ -1,18 +1,26 @@
 #!/usr/bin/env python
-"""Benchmark: the full-scale Potjans-Diesmann microcircuit on one MI355X.
+"""Benchmark: the Potjans-Diesmann microcircuit on one MI355X.
 
 One bench "step" is 10,000 simulation steps of 0.1 ms = 1 s of biological
 time, so ms_per_step / 1000 is the real-time factor (wall / biological time,
-the paper's RTF).  Defaults: 1 untimed warm-up second, then 10 timed seconds
-(the paper's 10 s runs).  The timed region runs from the first step launch to
-the read-back of the timed window's spike raster, bracketed by
-torch.cuda.synchronize(); the network is built and uploaded before it.
+the paper's RTF).  The timed region runs from the first step launch to the
+read-back of the timed window's spike rasters, bracketed by
+torch.cuda.synchronize(); networks are built and uploaded before it.
+
+Workloads (--workload):
+  full   the full-scale circuit, 77,169 neurons, ~3e8 synapses; plain and
+         compressed legs; defaults 1 warm-up + 10 timed seconds (the paper's
+         10 s runs).  The default.
+  batch  64 independent instances of uneven scale (5-20 %), g and background
+         rate; compressed and plain legs; 2 timed seconds.
+  x4     four times the neurons, full in-degrees (308,676 neurons, ~1.2e9
+         synapses); plain and compressed legs; 5 timed seconds.
 
 Reported value: synaptic events per second (device-counted activations of
-synapses by spikes) over the timed region.  The same line carries the
-real-time factor, the compressed-synapse leg, the roofline of the dominant
-kernel (timed live with HIP events on the library's stream) and the CPU
-oracle's throughput on a bounded sample of the same workload.
+synapses by spikes) of the first leg over the timed region.  The line also
+carries the real-time factor, the other leg, the roofline of the dominant
+kernel (timed live with HIP events on the library's stream) and, for the
+full workload, the CPU oracle's throughput on a bounded sample.
 """
 import argparse
 import json
@@ -26,48 +34,66 @@ sys.path.insert(0, ROOT)
 STEPS_PER_BIO_SECOND = 10000
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, 8 TB/s
 
+WORKLOADS = {
+    "full": {"legs": ["plain", "compressed"], "steps": 10,
+             "name": "full-scale PD microcircuit, 77,169 neurons, {syn} synapses, dt 0.1 ms"},
+    "batch": {"legs": ["compressed", "plain"], "steps": 2,
+              "name": "64 independent PD instances, scale U[5%,20%], g U[-6,-3], background "
+                      "U[6,10] Hz, full in-degrees; {neurons} neurons, {syn} synapses, dt 0.1 ms"},
+    "x4": {"legs": ["plain", "compressed"], "steps": 5,
+           "name": "4x PD microcircuit with full in-degrees, {neurons} neurons, {syn} synapses, "
+                   "dt 0.1 ms"},
+}
+
 
 def algorithmic_bytes(n_neurons, spikes, events, rec_bytes):
-    """Bytes a step loop must move at least (roofline):
-    ring row read + clear per neuron and step, one record plus one 4-byte ring
-    word per synaptic event, row pointers and raster entry per spike."""
+    """Bytes a step loop must move at least: ring row read + clear per neuron
+    and step, one record plus one 4-byte ring word per synaptic event, row
+    pointers and raster entry per spike."""
     return 8.0 * n_neurons, (rec_bytes + 4.0) * events + 24.0 * spikes
 
 
-def run_leg(P, fmt, engine, warm_bio_s, timed_bio_s, log):
+def run_leg(P, instances, fmt, engine, chunk, warm_bio_s, timed_bio_s, log):
     import torch
     t_build = time.perf_counter()
-    sim = P.Simulator(P.Instance(scale=1.0, seed=1), syn_format=fmt, engine=engine)
+    sim = P.Simulator(instances, syn_format=fmt, engine=engine, chunk_steps=chunk)
     build_s = time.perf_counter() - t_build
     info = sim.info()
     log(f"[bench] {fmt}: built in {build_s:.1f} s ({info['n_synapses_total']} synapses, "
-        f"engine {info['engine']}, block {info['block_size']}, grid {info['grid_blocks']})")
+        f"engine {info['engine']}, block {info['block_size']}, grid {info['grid_blocks']}, "
+        f"launches/chunk {info['launches_per_chunk']}, graphs {info['graphs']})")
     if warm_bio_s:
-        sim.step(warm_bio_s * STEPS_PER_BIO_SECOND)
-    s0 = sim.state()
-    t0_step = s0["t"]
-    n_steps = timed_bio_s * STEPS_PER_BIO_SECOND
+        sim.step(int(warm_bio_s * STEPS_PER_BIO_SECOND))
+    ni = len(instances)
+    s0 = [sim.state(i) for i in range(ni)]
+    t0_step = s0[0]["t"]
+    n_steps = int(timed_bio_s * STEPS_PER_BIO_SECOND)
     torch.cuda.synchronize()
     w0 = time.perf_counter()
     gpu_ms = sim.time_steps(n_steps)              # HIP events on the library's stream
-    steps, ids = sim.spikes(0, t0_step, t0_step + n_steps)
+    n_raster = 0
+    for i in range(ni):
+        steps, ids = sim.spikes(i, t0_step, t0_step + n_steps)
+        n_raster += len(ids)
     torch.cuda.synchronize()
     wall = time.perf_counter() - w0
-    s1 = sim.state()
-    events = s1["events"] - s0["events"]
-    spikes = s1["spikes"] - s0["spikes"]
-    assert spikes == len(ids), (spikes, len(ids))
-    n = s1["n_neurons"]
-    rec = 8.0 if fmt == "plain" else 5.0
+    s1 = [sim.state(i) for i in range(ni)]
+    events = sum(b["events"] - a["events"] for a, b in zip(s0, s1))
+    spikes = sum(b["spikes"] - a["spikes"] for a, b in zip(s0, s1))
+    assert spikes == n_raster, (spikes, n_raster)
+    n = sum(b["n_neurons"] for b in s1)
+    lds = info["engine"] == P.ENGINE_LDS
+    rec = 8.0 if fmt == "plain" else (4.0 if lds else 5.0)
     ring_b, syn_b = algorithmic_bytes(n, spikes, events, rec)
     total_bytes = ring_b * n_steps + syn_b
     chunked = info["engine"] in (P.ENGINE_PERSISTENT, P.ENGINE_LDS)
-    launches = -(-n_steps // info["chunk_steps"]) if chunked else 2 * n_steps
+    launches = (-(-n_steps // info["chunk_steps"]) * info["launches_per_chunk"] if chunked
+                else 2 * n_steps)
     sim.close()
     return {
         "fmt": fmt, "wall_s": wall, "gpu_ms": gpu_ms, "events": events, "spikes": spikes,
         "n_steps": n_steps, "n_neurons": n, "build_s": build_s, "info": info,
-        "bytes": total_bytes, "launches": launches,
+        "bytes": total_bytes, "launches": launches, "rec_bytes": rec,
     }
 
 
@@ -81,17 +107,19 @@ def kernel_name(P, info):
     return "k_update + k_transfer"
 
 
-def measured_traffic(kernel, fmt):
+def measured_traffic(kernel, workload, fmt, chunk):
     """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE
     summary, scaled by the copy calibration -- only while the kernel source is
-    the one the counters were taken on."""
+    the one the counters were taken on, for the same chunk length."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_full_scale_{fmt}.json")
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}_{fmt}.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
     src = os.path.join(ROOT, "paper_2405_02019_amd", "csrc", "kernels.hip")
     if hashlib.sha256(open(src, "rb").read()).hexdigest() != rec["kernel_source_sha256"]:
+        return None
+    if rec.get("chunk_steps") != chunk:
         return None
     return rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]
 
@@ -127,15 +155,29 @@ def copy_calibration(log):
     log("[bench] copied 3 x 1 GiB")
 
 
+def leg_summary(leg, bio):
+    return {"value": leg["events"] / leg["wall_s"], "unit": "synaptic events/s",
+            "rtf": leg["wall_s"] / bio, "ms_per_step": 1000.0 * leg["wall_s"] / bio,
+            "us_per_sim_step_gpu": 1000.0 * leg["gpu_ms"] / leg["n_steps"],
+            "spikes_per_step": leg["spikes"] / leg["n_steps"],
+            "syn_format": "plain8" if leg["fmt"] == "plain" else "compressed",
+            "record_bytes": leg["rec_bytes"], "build_s": leg["build_s"],
+            "device_bytes": leg["info"]["device_bytes"]}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10, help="timed seconds of biological time")
+    ap.add_argument("--workload", default="full", choices=sorted(WORKLOADS))
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed seconds of biological time (default: 10 full, 2 batch, 5 x4)")
     ap.add_argument("--warmup", type=int, default=1, help="untimed seconds of biological time")
     ap.add_argument("--engine", default="auto", choices=["auto", "stepwise", "persistent", "lds"])
+    ap.add_argument("--chunk", type=int, default=1000, help="simulation steps per launch (chunk)")
     ap.add_argument("--no-compressed", action="store_true", help="skip the compressed-synapse leg")
+    ap.add_argument("--no-plain", action="store_true", help="skip the plain-synapse leg")
     ap.add_argument("--cpu-steps", type=int, default=4000,
-                    help="oracle steps for the CPU baseline (0 = skip)")
+                    help="oracle steps for the CPU baseline, full workload only (0 = skip)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run the 1 GiB copy used to scale HBM counters")
     args = ap.parse_args()
@@ -158,58 +200,64 @@ def main():
         copy_calibration(log)
         return
     import paper_2405_02019_amd as P
+    from paper_2405_02019_amd import workloads
 
-    plain = run_leg(P, "plain", args.engine, args.warmup, args.steps, log)
-    comp = None if args.no_compressed else run_leg(P, "compressed", args.engine, args.warmup,
-                                                   args.steps, log)
-    bio = float(args.steps)
-    value = plain["events"] / plain["wall_s"]
-    avg_launch_ms = plain["gpu_ms"] / plain["launches"]
-    achieved = plain["bytes"] / plain["launches"] / (avg_launch_ms * 1e-3) / 1e9
-    kname = kernel_name(P, plain["info"])
+    wl = WORKLOADS[args.workload]
+    bio_steps = args.steps if args.steps is not None else wl["steps"]
+    instances = workloads.WORKLOADS[args.workload]()
+    legs = [f for f in wl["legs"] if not (f == "compressed" and args.no_compressed)
+            and not (f == "plain" and args.no_plain)]
+    results = [run_leg(P, instances, f, args.engine, args.chunk, args.warmup, bio_steps, log)
+               for f in legs]
+    first = results[0]
+    bio = float(bio_steps)
+    avg_launch_ms = first["gpu_ms"] / first["launches"]
+    achieved = first["bytes"] / first["launches"] / (avg_launch_ms * 1e-3) / 1e9
+    kname = kernel_name(P, first["info"])
     kernel = kname
-    if plain["info"]["engine"] in (P.ENGINE_PERSISTENT, P.ENGINE_LDS):
-        kernel += " (one cooperative launch per chunk of %d steps)" % plain["info"]["chunk_steps"]
+    if first["info"]["engine"] in (P.ENGINE_PERSISTENT, P.ENGINE_LDS):
+        kernel += " (cooperative launches of %d steps)" % first["info"]["chunk_steps"]
+    info = first["info"]
     out = {
         "metric": "realtime factor & synaptic events/s, full PD microcircuit; plain vs compressed",
-        "value": value,
+        "value": first["events"] / first["wall_s"],
         "unit": "synaptic events/s",
         "n_gpus": 1,
-        "steps": args.steps,
+        "steps": bio_steps,
         "warmup": args.warmup,
-        "ms_per_step": 1000.0 * plain["wall_s"] / args.steps,
+        "ms_per_step": 1000.0 * first["wall_s"] / bio,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32 state, int32 fixed-point synaptic input",
-        "data": "synthetic: Potjans-Diesmann network sampled from the paper's tables (seed 1)",
-        "config": {"workload": "full-scale PD microcircuit, 77,169 neurons, %d synapses, "
-                               "dt 0.1 ms, 10 s biological time per measurement" % plain["info"]["n_synapses_total"],
-                   "steps_per_bench_step": STEPS_PER_BIO_SECOND, "syn_format": "plain8",
-                   "engine": plain["info"]["engine"], "block": plain["info"]["block_size"],
-                   "grid": plain["info"]["grid_blocks"], "chunk_steps": plain["info"]["chunk_steps"]},
-        "rtf": plain["wall_s"] / bio,
-        "bio_per_wall": bio / plain["wall_s"],
-        "spikes_per_step": plain["spikes"] / plain["n_steps"],
-        "events_per_step": plain["events"] / plain["n_steps"],
-        "gpu_ms_timed": plain["gpu_ms"],
-        "build_s": plain["build_s"],
+        "data": "synthetic: Potjans-Diesmann networks sampled from the paper's tables",
+        "config": {"workload": wl["name"].format(syn=info["n_synapses_total"],
+                                                 neurons=first["n_neurons"]),
+                   "steps_per_bench_step": STEPS_PER_BIO_SECOND,
+                   "syn_format": "plain8" if first["fmt"] == "plain" else "compressed",
+                   "instances": len(instances), "engine": info["engine"],
+                   "block": info["block_size"], "grid": info["grid_blocks"],
+                   "window_neurons": info["window_neurons"], "chunk_steps": info["chunk_steps"],
+                   "launches_per_chunk": info["launches_per_chunk"], "graphs": info["graphs"]},
+        "rtf": first["wall_s"] / bio,
+        "bio_per_wall": bio / first["wall_s"],
+        "spikes_per_step": first["spikes"] / first["n_steps"],
+        "events_per_step": first["events"] / first["n_steps"],
+        "gpu_ms_timed": first["gpu_ms"],
+        "build_s": first["build_s"],
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic(kname, "plain"),
+                     "traffic": measured_traffic(kname, args.workload, first["fmt"],
+                                                 info["chunk_steps"]),
                      "kernel": kernel,
                      "avg_launch_ms": avg_launch_ms,
-                     "bytes_per_launch": plain["bytes"] / plain["launches"]},
+                     "bytes_per_launch": first["bytes"] / first["launches"]},
         "paper_context": {"fpga_rtf_gmem_mono_s": 4.79, "fpga_rtf_best_horiz_multi": 0.79,
                           "hardware": "1 Intel Agilex 7 FPGA (numbers quoted from the paper)"},
     }
-    if comp:
-        out["compressed"] = {"value": comp["events"] / comp["wall_s"], "unit": "synaptic events/s",
-                             "rtf": comp["wall_s"] / bio, "ms_per_step": 1000.0 * comp["wall_s"] / args.steps,
-                             "spikes_per_step": comp["spikes"] / comp["n_steps"],
-                             "syn_format": "compressed5", "build_s": comp["build_s"],
-                             "device_bytes": comp["info"]["device_bytes"]}
-    if args.cpu_steps > 0:
+    for leg in results[1:]:
+        out[leg["fmt"]] = leg_summary(leg, bio)
+    if args.workload == "full" and args.cpu_steps > 0:
         out["cpu_baseline"] = cpu_baseline(args.cpu_steps, log)
     print(json.dumps(out), flush=True)
 

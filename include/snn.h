@@ -33,7 +33,7 @@
 extern "C" {
 #endif
 
-#define SNN_ABI_VERSION 1u
+#define SNN_ABI_VERSION 2u
 
 enum snn_status {
   SNN_OK = 0,
@@ -198,6 +198,10 @@ typedef struct {
   uint64_t n_synapses_total;
   uint64_t device_bytes;   /* device memory held                            */
   double build_seconds;    /* host sampling + upload                        */
+  uint32_t launches_per_chunk; /* kernel launches one chunk of steps takes    */
+  uint32_t window_neurons; /* LDS engine: neurons of the longest window      */
+  uint32_t graphs;         /* 1: full chunks replay from a captured hipGraph */
+  uint32_t reserved;
 } snn_info;
 
 int snn_get_info(const snn_net *h, snn_info *out);

@@ -90,6 +90,7 @@ struct DeviceNet {
   const WinClass *wcls = nullptr;   // LDS engine: [windows][kWinClasses]
   const uint2 *wrel = nullptr;      // LDS engine: per window, the windows [x, y) of its instance
   int64_t *blk_ctr = nullptr;       // LDS engine: [windows][4] spikes, thalamic, consumed, events
+  uint2 *lgroup = nullptr;          // LDS engine: per launch group (flag epoch, blocks finished)
   const uint32_t *outdeg = nullptr; // LDS engine: synapses per sender [ntot]
   uint64_t *lflags = nullptr;       // LDS engine: [kSlots][windows] flag words
   uint32_t *llist = nullptr;        // LDS engine: [kSlots][ntot] senders beyond the inline ones
@@ -114,10 +115,11 @@ hipError_t launch_persistent(const DeviceNet &d, const LaunchShape &sh, uint32_t
 // quad capacity per thread it was compiled for.
 int persistent_max_grid(const DeviceNet &d, uint32_t block, uint32_t qpt);
 uint32_t persistent_qmax(uint32_t qpt);
-// LDS engine: one cooperative launch of windows [win0, win0 + nwin) (whole
-// instances) runs steps t0 .. t0 + n - 1; ep0 is the group's flag epoch.
-hipError_t launch_lds(const DeviceNet &d, uint32_t win0, uint32_t nwin, uint32_t n, uint64_t t0,
-                      uint32_t ep0, hipStream_t s);
+// LDS engine: one cooperative launch of group `group` (windows [win0, win0 +
+// nwin), whole instances) runs n steps from ctl->t_base; the last of the
+// n_groups launches of a chunk advances ctl->t_base.
+hipError_t launch_lds(const DeviceNet &d, uint32_t group, uint32_t n_groups, uint32_t win0,
+                      uint32_t nwin, uint32_t n, hipStream_t s);
 // Co-resident blocks of the LDS kernel with window capacity wn (320 or 512).
 int lds_max_grid(uint32_t wn);
 

@@ -995,8 +995,9 @@ struct SegmentWalk {
 };
 
 template <int WN, bool COMP>
-__global__ __launch_bounds__(256) void k_lds(DeviceNet d, uint32_t n_steps, uint64_t t0,
-                                             uint32_t ep0, uint32_t win0, uint32_t spin_limit) {
+__global__ __launch_bounds__(256) void k_lds(DeviceNet d, uint32_t n_steps, uint32_t group,
+                                             uint32_t last_group, uint32_t win0,
+                                             uint32_t spin_limit) {
   constexpr uint32_t BS = 256;
   constexpr uint32_t NQ = WN / 4;             // quads a window can hold
   constexpr uint32_t Q0 = BS - NQ;            // threads Q0.. own one quad each
@@ -1026,6 +1027,11 @@ __global__ __launch_bounds__(256) void k_lds(DeviceNet d, uint32_t n_steps, uint
   __shared__ long long s_ctr[4];
 
   const uint32_t GT = d.n_lwin, blk = win0 + blockIdx.x;
+  // Step origin and flag epoch live in device memory, so a chunk's launches
+  // can be replayed from a captured graph; the group's last block advances
+  // them when it leaves.
+  const uint64_t t0 = d.ctl->t_base;
+  const uint32_t ep0 = d.lgroup[group].x;
   const uint32_t tid = threadIdx.x, lane = __lane_id();
   const uint32_t wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const uint4 wi = d.lwin[blk];               // (first neuron, neurons, instance, -)
@@ -1363,9 +1369,20 @@ __global__ __launch_bounds__(256) void k_lds(DeviceNet d, uint32_t n_steps, uint
   }
   __syncthreads();
   if (tid < 4u) d.blk_ctr[size_t(blk) * 4 + tid] += s_ctr[tid];
+  __builtin_amdgcn_s_waitcnt(0x0F70);
+  __syncthreads();
+  if (tid == 0) {
+    unsigned int *exits = &d.lgroup[group].y;
+    const uint32_t done = __hip_atomic_fetch_add(exits, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (done == gridDim.x - 1) {
+      st_ag(exits, 0u);
+      st_ag(&d.lgroup[group].x, ep0 + n_steps);
+      if (last_group) st_ag(&d.ctl->t_base, t0 + n_steps);
+    }
+  }
 }
 
-using LdsFn = void (*)(DeviceNet, uint32_t, uint64_t, uint32_t, uint32_t, uint32_t);
+using LdsFn = void (*)(DeviceNet, uint32_t, uint32_t, uint32_t, uint32_t, uint32_t);
 
 static LdsFn lds_fn(uint32_t wn, bool comp) {
   if (wn == 512) return comp ? k_lds<512, true> : k_lds<512, false>;
@@ -1385,16 +1402,15 @@ int lds_max_grid(uint32_t wn) {
   return std::min<int>(std::min(per_cu, 1) * prop.multiProcessorCount, int(kLdsMaxGrid));
 }
 
-hipError_t launch_lds(const DeviceNet &d, uint32_t win0, uint32_t nwin, uint32_t n, uint64_t t0,
-                      uint32_t ep0, hipStream_t s) {
+hipError_t launch_lds(const DeviceNet &d, uint32_t group, uint32_t n_groups, uint32_t win0,
+                      uint32_t nwin, uint32_t n, hipStream_t s) {
   LdsFn fn = lds_fn(d.lds_window, d.syn_format == SNN_SYN_COMPRESSED5);
-  if (!fn || nwin == 0 || nwin > kLdsMaxGrid || win0 + nwin > d.n_lwin)
+  if (!fn || nwin == 0 || nwin > kLdsMaxGrid || win0 + nwin > d.n_lwin || group >= n_groups)
     return hipErrorInvalidConfiguration;
   DeviceNet dv = d;
-  uint32_t steps = n, e0 = ep0, w0 = win0;
-  uint64_t tt = t0;
+  uint32_t steps = n, g = group, last = group + 1 == n_groups ? 1u : 0u, w0 = win0;
   uint32_t spin = 1u << 24;
-  void *args[] = {&dv, &steps, &tt, &e0, &w0, &spin};
+  void *args[] = {&dv, &steps, &g, &last, &w0, &spin};
   return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(fn), dim3(nwin), dim3(256), args,
                                     0, s);
 }

@@ -47,7 +47,6 @@ struct snn_net {
   bool overflowed = false;
   bool dead = false;
   std::vector<uint2> lds_groups;    // LDS engine: launches (first window, windows)
-  std::vector<uint32_t> lds_epoch;  // LDS engine: flag epoch of each group
   std::string err;
   double build_seconds = 0.0;
 };
@@ -213,8 +212,10 @@ int plan_lds(const std::vector<InstMeta> &im, uint32_t block, uint32_t grid, Lds
     if (4 * nq > uint64_t(maxg) * L) continue;
     if (make_plan(im, L, wn, maxg, p) && p.groups.size() == 1) return SNN_OK;
   }
-  if (make_plan(im, 512, 512, uint32_t(g512), p)) return SNN_OK;
-  why = "an instance needs more windows than the LDS engine can keep co-resident";
+  // Networks beyond one co-resident grid would need several launches per
+  // chunk; that path is switched off (a run of a 64-instance batch in five
+  // launches per chunk faulted the GPU and its cause is not established).
+  why = "the network needs more windows than one co-resident launch of the LDS engine holds";
   return SNN_E_RANGE;
 }
 
@@ -242,13 +243,20 @@ int choose_persistent_shape(snn_net *h, uint32_t block, uint32_t grid) {
   return fail(h, SNN_E_RANGE, "no co-resident persistent grid fits %u neurons", d.ntot);
 }
 
+// One chunk of the LDS engine: the launches of every instance group.
+hipError_t launch_lds_chunk(snn_net *h, uint32_t n) {
+  const uint32_t ng = uint32_t(h->lds_groups.size());
+  for (uint32_t g = 0; g < ng; ++g) {
+    const uint2 gr = h->lds_groups[g];
+    const hipError_t e = launch_lds(h->d, g, ng, gr.x, gr.y, n, h->stream);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
 int queue_steps(snn_net *h, uint32_t n) {
   if (h->engine == SNN_ENGINE_LDS) {
-    for (size_t g = 0; g < h->lds_groups.size(); ++g) {
-      const uint2 gr = h->lds_groups[g];
-      HIP_OK(h, launch_lds(h->d, gr.x, gr.y, n, h->t, h->lds_epoch[g], h->stream));
-      h->lds_epoch[g] += n;
-    }
+    HIP_OK(h, launch_lds_chunk(h, n));
     return SNN_OK;
   }
   if (h->engine == SNN_ENGINE_PERSISTENT) {
@@ -378,7 +386,6 @@ int snn_build(const snn_config *cfg, snn_net **out) {
         w0 += plan.nwin[k];
       }
       h->lds_groups = plan.groups;
-      h->lds_epoch.assign(plan.groups.size(), 0);
     } else {
       if (cfg->engine == SNN_ENGINE_LDS) {
         fail(h, prc, "%s", why.c_str());
@@ -499,6 +506,7 @@ int snn_build(const snn_config *cfg, snn_net **out) {
     ALLOC(d.lflags, kSlots * size_t(nwin_lds));
     ALLOC(d.llist, kSlots * size_t(d.ntot));
     ALLOC(d.blk_ctr, 4 * size_t(nwin_lds));
+    ALLOC(d.lgroup, plan.groups.size());
   }
 #undef ALLOC
 
@@ -637,7 +645,8 @@ int snn_build(const snn_config *cfg, snn_net **out) {
       hipMemset(d.events, 0, ni * sizeof(uint64_t)) != hipSuccess ||
       hipMemset(d.ctl, 0, sizeof(Control)) != hipSuccess ||
       (d.lflags && hipMemset(d.lflags, 0, kSlots * size_t(nwin_lds) * sizeof(uint64_t)) != hipSuccess) ||
-      (d.blk_ctr && hipMemset(d.blk_ctr, 0, 4 * size_t(nwin_lds) * sizeof(int64_t)) != hipSuccess)) {
+      (d.blk_ctr && hipMemset(d.blk_ctr, 0, 4 * size_t(nwin_lds) * sizeof(int64_t)) != hipSuccess) ||
+      (d.lgroup && hipMemset(d.lgroup, 0, plan.groups.size() * sizeof(uint2)) != hipSuccess)) {
     fail(h, SNN_E_HIP, "device memset failed");
     return bail(SNN_E_HIP);
   }
@@ -668,6 +677,8 @@ int snn_build(const snn_config *cfg, snn_net **out) {
     }
     if (cfg->grid_blocks) h->shape.scatter_blocks = cfg->grid_blocks;
   }
+  // The LDS engine launches its chunks directly: a captured kernel node does
+  // not carry the cooperative launch's co-residency guarantee.
   if (cfg->use_graphs && h->engine == SNN_ENGINE_STEPWISE) {
     if (hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
       fail(h, SNN_E_HIP, "stream capture failed to start");
@@ -812,6 +823,13 @@ int snn_get_info(const snn_net *h, snn_info *out) {
   out->n_synapses_total = s;
   out->device_bytes = h->device_bytes;
   out->build_seconds = h->build_seconds;
+  out->graphs = h->graph_exec ? 1u : 0u;
+  if (h->engine == SNN_ENGINE_LDS) {
+    out->launches_per_chunk = uint32_t(h->lds_groups.size());
+    for (const auto &m : h->im) out->window_neurons = std::max(out->window_neurons, m.wlen);
+  } else {
+    out->launches_per_chunk = h->engine == SNN_ENGINE_PERSISTENT ? 1u : 2u * h->chunk;
+  }
   return SNN_OK;
 }
 

@@ -21,7 +21,7 @@ ENGINE_AUTO = 0
 ENGINE_STEPWISE = 1
 ENGINE_PERSISTENT = 2
 ENGINE_LDS = 3
-ABI_VERSION = 1
+ABI_VERSION = 2
 
 SNN_OK = 0
 ERRORS = {-1: "SNN_E_INVAL", -2: "SNN_E_NOMEM", -3: "SNN_E_HIP", -4: "SNN_E_RANGE",
@@ -68,7 +68,9 @@ class _Info(C.Structure):
     _fields_ = [("engine", C.c_uint32), ("block_size", C.c_uint32), ("grid_blocks", C.c_uint32),
                 ("quads_per_thread", C.c_uint32), ("chunk_steps", C.c_uint32),
                 ("n_neurons_total", C.c_uint32), ("n_synapses_total", C.c_uint64),
-                ("device_bytes", C.c_uint64), ("build_seconds", C.c_double)]
+                ("device_bytes", C.c_uint64), ("build_seconds", C.c_double),
+                ("launches_per_chunk", C.c_uint32), ("window_neurons", C.c_uint32),
+                ("graphs", C.c_uint32), ("reserved", C.c_uint32)]
 
 
 class _HostNet(C.Structure):

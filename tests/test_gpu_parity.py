@@ -164,6 +164,31 @@ def test_batched_instances_each_bit_exact(P, oracle):
                 assert_parity(sim, k, net, osim)
 
 
+@pytest.mark.skip(reason="LDS runs in several launches per chunk are switched off: a 64-instance "
+                         "batch run in five launches per chunk (graph-captured) faulted the GPU; "
+                         "cause not established")
+def test_lds_instance_groups_bit_exact(P, oracle):
+    """Instances beyond one co-resident grid (18 x 10 % circuits, 139k
+    neurons) run as several LDS launches per chunk, each instance still equal
+    to its own oracle run; with and without graph-captured chunks, across
+    ragged chunk pieces."""
+    rng = np.random.default_rng(5)
+    insts = [P.Instance(scale=0.1, seed=40 + i, g=float(rng.uniform(-6, -3)),
+                        bg_rate_hz=float(rng.uniform(6, 10))) for i in range(18)]
+    for fmt, wmode, graphs in [("plain", 0, True), ("compressed", 1, False)]:
+        say("lds groups", fmt, "graphs", graphs)
+        with P.Simulator(insts, syn_format=fmt, engine="lds", chunk_steps=50,
+                         use_graphs=graphs) as sim:
+            info = sim.info()
+            say("lds groups info", info)
+            assert info["engine"] == P.ENGINE_LDS and info["launches_per_chunk"] >= 2
+            sim.step(70)
+            sim.step(80)
+            for k, inst in enumerate(insts):
+                net, osim = run_oracle(oracle, inst, wmode, 150)
+                assert_parity(sim, k, net, osim, ring=(k % 5 == 0))
+
+
 @pytest.fixture(scope="module")
 def full_oracle(oracle):
     """Oracle run of the full-scale microcircuit, 300 steps."""
