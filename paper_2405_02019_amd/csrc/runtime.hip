@@ -41,7 +41,8 @@ struct snn_net {
   size_t device_bytes = 0;
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;
-  std::vector<uint64_t> raster;     // drained, sorted by (step, global id)
+  std::vector<uint64_t> raster;     // drained; sorted by (step, global id) up to raster_sorted
+  size_t raster_sorted = 0;         // later drains hold later steps: only the tail needs sorting
   uint64_t t = 0;
   uint64_t pending = 0;             // worst-case raster entries since the last drain
   bool overflowed = false;
@@ -127,11 +128,39 @@ int drain(snn_net *h) {
     h->raster.resize(old + m);
     HIP_OK(h, hipMemcpy(h->raster.data() + old, h->d.raster, m * sizeof(uint64_t),
                         hipMemcpyDeviceToHost));
-    std::sort(h->raster.begin() + old, h->raster.end());
   }
   HIP_OK(h, launch_reset_raster(h->d, h->stream));
   h->pending = 0;
   return SNN_OK;
+}
+
+// Sorts raster entries (step << 32 | id) from index `from` on: a counting
+// sort by step (the entries of the tail span few steps), then each step's
+// handful of ids.
+void sort_raster_tail(std::vector<uint64_t> &r, size_t from) {
+  const size_t n = r.size() - from;
+  if (n < 2) return;
+  uint64_t lo = ~0ull, hi = 0;
+  for (size_t i = from; i < r.size(); ++i) {
+    lo = std::min(lo, r[i] >> 32);
+    hi = std::max(hi, r[i] >> 32);
+  }
+  const uint64_t span = hi - lo + 1;
+  if (span > 4 * n + 1024) {   // sparse in time: a comparison sort is cheaper
+    std::sort(r.begin() + from, r.end());
+    return;
+  }
+  std::vector<size_t> start(span + 1, 0);
+  for (size_t i = from; i < r.size(); ++i) ++start[(r[i] >> 32) - lo + 1];
+  for (uint64_t k = 0; k < span; ++k) start[k + 1] += start[k];
+  std::vector<uint64_t> out(n);
+  for (size_t i = from; i < r.size(); ++i) out[start[(r[i] >> 32) - lo]++] = r[i];
+  size_t a = 0;
+  for (uint64_t k = 0; k < span; ++k) {   // start[k] is now the end of step lo + k
+    std::sort(out.begin() + a, out.begin() + start[k]);
+    a = start[k];
+  }
+  std::copy(out.begin(), out.end(), r.begin() + from);
 }
 
 uint64_t spike_bound(const snn_net *h, uint64_t steps) {
@@ -459,7 +488,12 @@ int snn_build(const snn_config *cfg, snn_net **out) {
   uint8_t *d_d8 = nullptr;
   const bool comp = cfg->syn_format == SNN_SYN_COMPRESSED5;
   uint64_t cap = cfg->raster_capacity;
-  if (!cap) cap = std::max<uint64_t>(uint64_t(1) << 20, uint64_t(256) * d.ntot);
+  // Default: room for the worst case of about 20,000 steps (a neuron spikes
+  // at most every 21 steps), so that drains -- a stream synchronisation each
+  // -- are rare; at most 2^30 entries.
+  if (!cap)
+    cap = std::min<uint64_t>(uint64_t(1) << 30,
+                             std::max<uint64_t>(uint64_t(1) << 20, uint64_t(1024) * d.ntot));
   cap = std::max<uint64_t>(cap, 2 * h->n_real + 64);
   d.raster_cap = cap;
   int rc = SNN_OK;
@@ -727,6 +761,10 @@ int snn_read_spikes(snn_net *h, uint32_t inst, uint64_t t0, uint64_t t1, uint32_
   const InstMeta &m = h->im[inst];
   t0 = std::min<uint64_t>(t0, 0xFFFFFFFFull);
   t1 = std::min<uint64_t>(t1, 0x100000000ull);
+  if (h->raster_sorted < h->raster.size()) {
+    sort_raster_tail(h->raster, h->raster_sorted);
+    h->raster_sorted = h->raster.size();
+  }
   auto lo = std::lower_bound(h->raster.begin(), h->raster.end(), t0 << 32);
   auto hi = t1 >= 0x100000000ull ? h->raster.end()
                                  : std::lower_bound(h->raster.begin(), h->raster.end(), t1 << 32);
