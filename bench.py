@@ -64,6 +64,13 @@ def run_leg(P, instances, fmt, engine, chunk, warm_bio_s, timed_bio_s, log):
         f"launches/chunk {info['launches_per_chunk']}, graphs {info['graphs']})")
     if warm_bio_s:
         sim.step(int(warm_bio_s * STEPS_PER_BIO_SECOND))
+    tune = None
+    if info["engine"] != P.ENGINE_LDS:   # the LDS engine's shape is fixed by its layout
+        tune = sim.autotune(500)
+        info = sim.info()
+        log(f"[bench] {fmt}: autotuned over {tune['candidates']} shapes: block {tune['block_size']}, "
+            f"grid {tune['grid_blocks']}, quads/thread {tune['quads_per_thread']}, "
+            f"{tune['us_per_step_first']:.2f} -> {tune['us_per_step_best']:.2f} us/step")
     ni = len(instances)
     s0 = [sim.state(i) for i in range(ni)]
     t0_step = s0[0]["t"]
@@ -93,7 +100,7 @@ def run_leg(P, instances, fmt, engine, chunk, warm_bio_s, timed_bio_s, log):
     return {
         "fmt": fmt, "wall_s": wall, "gpu_ms": gpu_ms, "events": events, "spikes": spikes,
         "n_steps": n_steps, "n_neurons": n, "build_s": build_s, "info": info,
-        "bytes": total_bytes, "launches": launches, "rec_bytes": rec,
+        "bytes": total_bytes, "launches": launches, "rec_bytes": rec, "tune": tune,
     }
 
 
@@ -238,7 +245,8 @@ def main():
                    "instances": len(instances), "engine": info["engine"],
                    "block": info["block_size"], "grid": info["grid_blocks"],
                    "window_neurons": info["window_neurons"], "chunk_steps": info["chunk_steps"],
-                   "launches_per_chunk": info["launches_per_chunk"], "graphs": info["graphs"]},
+                   "launches_per_chunk": info["launches_per_chunk"], "graphs": info["graphs"],
+                   "autotuned": first["tune"] is not None},
         "rtf": first["wall_s"] / bio,
         "bio_per_wall": bio / first["wall_s"],
         "spikes_per_step": first["spikes"] / first["n_steps"],

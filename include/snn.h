@@ -206,6 +206,30 @@ typedef struct {
 
 int snn_get_info(const snn_net *h, snn_info *out);
 
+/* ---- launch-shape tuning ----------------------------------------------- */
+typedef struct {
+  uint32_t engine;
+  uint32_t candidates;        /* shapes timed                                  */
+  uint32_t block_size;        /* shape adopted                                 */
+  uint32_t grid_blocks;
+  uint32_t quads_per_thread;
+  uint32_t reserved;
+  double us_per_step_first;   /* the handle's shape before tuning              */
+  double us_per_step_best;    /* the adopted shape                             */
+} snn_tune_report;
+
+/*
+ * snn_autotune -- time candidate launch shapes of the handle's engine on the
+ * live simulation and keep the fastest.  Each candidate runs trial_steps
+ * steps for real (they advance the simulation; every shape gives the same
+ * results).  Persistent engine: block size x quads per thread, each at the
+ * smallest co-resident grid; stepwise engine: grid of the transfer kernel
+ * (the chunk graph is captured again); the LDS engine's shape is fixed by its
+ * storage layout and is reported as the one candidate.  Synchronises.
+ * Errors: as snn_step_n; SNN_E_INVAL for trial_steps = 0 or a NULL argument.
+ */
+int snn_autotune(snn_net *h, uint32_t trial_steps, snn_tune_report *out);
+
 /*
  * snn_time_steps -- queue n_steps steps (as snn_step_n) between two HIP events
  * recorded on the handle's stream and return the elapsed milliseconds.

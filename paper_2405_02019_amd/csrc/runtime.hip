@@ -871,6 +871,86 @@ int snn_get_info(const snn_net *h, snn_info *out) {
   return SNN_OK;
 }
 
+int snn_autotune(snn_net *h, uint32_t trial_steps, snn_tune_report *out) {
+  if (!h || !out) return fail(h, SNN_E_INVAL, "NULL argument");
+  if (!trial_steps) return fail(h, SNN_E_INVAL, "trial_steps must be positive");
+  if (h->dead) return fail(h, SNN_E_DEVICE, "the handle is unusable after a device failure");
+  std::memset(out, 0, sizeof *out);
+  out->engine = h->engine;
+  auto timed = [&](double *us) -> int {
+    double ms = 0.0;
+    const int rc = snn_time_steps(h, trial_steps, &ms);
+    *us = 1000.0 * ms / trial_steps;
+    return rc;
+  };
+  // Stepwise: the chunk graph bakes the transfer grid in; capture it again.
+  auto recapture = [&]() -> int {
+    if (!h->graph_exec) return SNN_OK;
+    (void)hipGraphExecDestroy(h->graph_exec);
+    (void)hipGraphDestroy(h->graph);
+    h->graph_exec = nullptr;
+    h->graph = nullptr;
+    HIP_OK(h, hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
+    const hipError_t le = launch_stepwise(h->d, h->shape, h->chunk, h->stream);
+    const hipError_t ce = hipStreamEndCapture(h->stream, &h->graph);
+    if (le != hipSuccess || ce != hipSuccess ||
+        hipGraphInstantiate(&h->graph_exec, h->graph, nullptr, nullptr, 0) != hipSuccess)
+      return fail(h, SNN_E_HIP, "graph capture of a %u-step chunk failed", h->chunk);
+    return SNN_OK;
+  };
+  std::vector<LaunchShape> cands;
+  const LaunchShape first = h->shape;
+  cands.push_back(first);
+  if (h->engine == SNN_ENGINE_PERSISTENT) {
+    for (uint32_t b : {128u, 256u, 512u, 1024u})
+      for (uint32_t q : {1u, 2u, 4u, 8u}) {
+        const int maxg = persistent_max_grid(h->d, b, q);
+        const uint32_t g = (h->d.nquads + b * q - 1) / (b * q);
+        if (maxg <= 0 || g == 0 || g > uint32_t(maxg)) continue;
+        LaunchShape s = first;
+        s.block = b;
+        s.grid = g;
+        s.qpt = (h->d.nquads + g * b - 1) / (g * b);
+        if (s.block != first.block || s.grid != first.grid || s.qpt != first.qpt) cands.push_back(s);
+      }
+  } else if (h->engine == SNN_ENGINE_STEPWISE) {
+    for (uint32_t sb : {256u, 512u, 1024u, 2048u, 4096u})
+      if (sb != first.scatter_blocks) {
+        LaunchShape s = first;
+        s.scatter_blocks = sb;
+        cands.push_back(s);
+      }
+  }
+  double best = 0.0;
+  size_t bi = 0;
+  for (size_t i = 0; i < cands.size(); ++i) {
+    h->shape = cands[i];
+    int rc = h->engine == SNN_ENGINE_STEPWISE ? recapture() : SNN_OK;
+    double us = 0.0;
+    if (!rc) rc = timed(&us);
+    if (rc) {
+      h->shape = first;
+      return rc;
+    }
+    if (i == 0) out->us_per_step_first = us;
+    if (i == 0 || us < best) {
+      best = us;
+      bi = i;
+    }
+  }
+  h->shape = cands[bi];
+  if (h->engine == SNN_ENGINE_STEPWISE) {
+    const int rc = recapture();
+    if (rc) return rc;
+  }
+  out->candidates = uint32_t(cands.size());
+  out->block_size = h->shape.block;
+  out->grid_blocks = h->engine == SNN_ENGINE_STEPWISE ? h->shape.scatter_blocks : h->shape.grid;
+  out->quads_per_thread = h->shape.qpt;
+  out->us_per_step_best = best;
+  return SNN_OK;
+}
+
 int snn_time_steps(snn_net *h, uint64_t n_steps, double *elapsed_ms) {
   if (!h || !elapsed_ms) return fail(h, SNN_E_INVAL, "NULL argument");
   hipEvent_t a, b;

@@ -73,6 +73,13 @@ class _Info(C.Structure):
                 ("graphs", C.c_uint32), ("reserved", C.c_uint32)]
 
 
+class _Tune(C.Structure):
+    _fields_ = [("engine", C.c_uint32), ("candidates", C.c_uint32), ("block_size", C.c_uint32),
+                ("grid_blocks", C.c_uint32), ("quads_per_thread", C.c_uint32),
+                ("reserved", C.c_uint32), ("us_per_step_first", C.c_double),
+                ("us_per_step_best", C.c_double)]
+
+
 class _HostNet(C.Structure):
     _fields_ = [("n_neurons", C.c_uint32), ("n_synapses", C.c_uint64),
                 ("pop_offset", C.c_uint32 * 9), ("row_ptr", C.POINTER(C.c_uint64)),
@@ -94,6 +101,7 @@ SIGNATURES = {
     "snn_last_error": (C.c_char_p, [C.c_void_p]),
     "snn_get_info": (C.c_int, [C.c_void_p, C.POINTER(_Info)]),
     "snn_time_steps": (C.c_int, [C.c_void_p, C.c_uint64, C.POINTER(C.c_double)]),
+    "snn_autotune": (C.c_int, [C.c_void_p, C.c_uint32, C.POINTER(_Tune)]),
     "snn_sample_network": (C.c_int, [C.POINTER(_Inst), C.c_uint32, C.c_int32,
                                      C.POINTER(C.POINTER(_HostNet))]),
     "snn_sample_network_windows": (C.c_int, [C.POINTER(_Inst), C.c_uint32, C.c_uint32, C.c_int32,
@@ -284,6 +292,13 @@ class Simulator:
         if ring:
             out["W"] = W
         return out
+
+    def autotune(self, trial_steps=200):
+        """Time the engine's candidate launch shapes on the live simulation
+        (trial_steps real steps each) and keep the fastest; returns the report."""
+        r = _Tune()
+        _check(lib().snn_autotune(self.h, int(trial_steps), C.byref(r)), self.h)
+        return {f: getattr(r, f) for f, _ in _Tune._fields_}
 
     def info(self):
         inf = _Info()

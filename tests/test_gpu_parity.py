@@ -189,6 +189,24 @@ def test_lds_instance_groups_bit_exact(P, oracle):
                 assert_parity(sim, k, net, osim, ring=(k % 5 == 0))
 
 
+@pytest.mark.parametrize("engine", ["persistent", "stepwise", "lds"])
+def test_autotune_keeps_results_bit_exact(P, oracle, engine):
+    """The shape tuner runs its trials on the live simulation: afterwards the
+    state equals the oracle's after the same number of steps."""
+    insts = [P.Instance(scale=0.02, seed=21), P.Instance(scale=0.01, seed=22, g=-5.0)]
+    say("autotune", engine)
+    with P.Simulator(insts, engine=engine, chunk_steps=40) as sim:
+        rep = sim.autotune(25)
+        say("autotune report", rep)
+        assert rep["candidates"] >= (1 if engine == "lds" else 2)
+        assert rep["us_per_step_best"] > 0 and rep["us_per_step_best"] <= rep["us_per_step_first"]
+        total = rep["candidates"] * 25 + 60
+        sim.step(60)
+        for k, inst in enumerate(insts):
+            net, osim = run_oracle(oracle, inst, 0, total)
+            assert_parity(sim, k, net, osim)
+
+
 @pytest.fixture(scope="module")
 def full_oracle(oracle):
     """Oracle run of the full-scale microcircuit, 300 steps."""
