@@ -921,56 +921,59 @@ __device__ __forceinline__ uint32_t sender_gid(const DeviceNet &d, uint32_t j, u
   return w0 + ld_ag(d.llist + size_t(lslot) * d.ntot + w0 + kk);
 }
 
-// UR record slots per lane.  load() walks this wave's senders of a batch
-// (lane l holds the segment address and capacity of the wave's sender l) in
-// 64-record pieces, one piece per slot;
-// apply() adds the loaded records into rows (t_src + delay).  Unused slots
-// and empty record slots (delay 0) add nothing.
+// UR record slots per lane.  The wave's senders of a batch are held one per
+// lane (segment address and capacity); their segments are cut into 64-record
+// pieces, numbered sender by sender.  load() takes the next UR pieces, one per
+// slot: the sender of piece P is the last lane whose first piece is <= P (a
+// ballot), so a piece's address costs a few scalar operations and no branch.
+// apply() adds the loaded records into rows (t_src + delay).  Unused slots and
+// empty record slots (delay 0) add nothing.
 template <bool COMP, int UR>
 struct SegmentWalk {
   uint64_t rec[COMP ? 1 : UR];
   uint32_t r4[COMP ? UR : 1];
   uint64_t base_l;   // lane l: segment of the wave's sender l
   uint32_t cap_l;
-  uint32_t nl;       // senders of this wave
-  uint32_t l, c0;    // cursor: sender, offset in its segment
-  uint32_t cap;
-  uint64_t base;
+  uint32_t p_l;      // lane l: number of the sender's first piece
+  uint32_t np;       // pieces of the batch (wave-uniform)
+  uint32_t p0;       // next piece
 
-  // Lane l holds the segment of the wave's sender l (cap 0 past the end);
-  // n_l (wave-uniform) senders.  All cursor state is scalar.
-  __device__ __forceinline__ void begin(uint64_t base_lane, uint32_t cap_lane, uint32_t n_l) {
+  // Lane l holds the segment of the wave's sender l (capacity 0 past the end).
+  __device__ __forceinline__ void begin(uint64_t base_lane, uint32_t cap_lane) {
+    const uint32_t lane = __lane_id();
     base_l = base_lane;
     cap_l = cap_lane;
-    nl = n_l;
-    l = 0;
-    c0 = 0;
-    pick(0);
+    const uint32_t n = (cap_lane + 63u) >> 6;
+    uint32_t x = n;   // inclusive scan of the piece counts
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint32_t y = __shfl_up(x, o);
+      if (lane >= uint32_t(o)) x += y;
+    }
+    p_l = x - n;
+    np = __builtin_amdgcn_readlane(x, 63);
+    p0 = 0;
   }
-  __device__ __forceinline__ void pick(uint32_t i) {
-    cap = __builtin_amdgcn_readlane(cap_l, i);
-    base = (uint64_t(__builtin_amdgcn_readlane(uint32_t(base_l >> 32), i)) << 32) |
-           __builtin_amdgcn_readlane(uint32_t(base_l), i);
-  }
-  __device__ __forceinline__ bool more() const { return l < nl; }
+  __device__ __forceinline__ bool more() const { return p0 < np; }
 
   __device__ __forceinline__ void load(const DeviceNet &d) {
     const uint32_t lane = __lane_id();
 #pragma unroll
     for (int u = 0; u < UR; ++u) {
-      while (l < nl && c0 >= cap) {
-        ++l;
-        c0 = 0;
-        if (l < nl) pick(l);
-      }
-      const bool ok = l < nl && c0 + lane < cap;
-      const uint64_t idx = base + c0 + lane;
+      const uint32_t P = p0 + uint32_t(u);
+      // Lanes past the last sender have p_l = np > P, so they never count.
+      const uint32_t s = uint32_t(__popcll(__ballot(p_l <= P))) - 1u;
+      const uint32_t k = P - __builtin_amdgcn_readlane(p_l, s);
+      const uint32_t cap = __builtin_amdgcn_readlane(cap_l, s);
+      const uint64_t base = ((uint64_t(__builtin_amdgcn_readlane(uint32_t(base_l >> 32), s)) << 32) |
+                             __builtin_amdgcn_readlane(uint32_t(base_l), s)) + 64u * k;
+      const bool ok = P < np && 64u * k + lane < cap;
       if (COMP)
-        r4[u] = ok ? __builtin_nontemporal_load(d.rec4 + idx) : 0u;
+        r4[u] = ok ? __builtin_nontemporal_load(d.rec4 + base + lane) : 0u;
       else
-        rec[u] = ok ? __builtin_nontemporal_load(d.rec8 + idx) : 0ull;
-      c0 += 64;
+        rec[u] = ok ? __builtin_nontemporal_load(d.rec8 + base + lane) : 0ull;
     }
+    p0 += UR;
   }
 
   template <int WN>
@@ -1319,7 +1322,7 @@ __global__ __launch_bounds__(256) void k_lds(DeviceNet d, uint32_t n_steps, uint
         base_lane = s_cbase[ci] + uint64_t(gid - s_cf[ci]) * cap_lane;
       }
       SegmentWalk<COMP, UR> sw;
-      sw.begin(base_lane, cap_lane, n_l);
+      sw.begin(base_lane, cap_lane);
       while (sw.more()) {
         sw.load(d);
         if (!drawn) {   // T_t while the first records are in flight
