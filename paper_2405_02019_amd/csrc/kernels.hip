@@ -878,9 +878,9 @@ hipError_t launch_persistent(const DeviceNet &d, const LaunchShape &sh, uint32_t
 // Iteration it (t = t0 + it):
 //   (a) complete step t-1 from ring row t-1 and the thalamic counts T_{t-1};
 //   (b) decide step t (membrane update only) and publish its flag;
-//   (c) wait for the flags of step t-1, stage those senders, issue their
-//       record loads, draw the thalamic counts T_t while the loads are in
-//       flight, and add the records into rows t .. t+62.
+//   (c) wave 0 waits for the flags of step t-1 while waves 1-3 draw the
+//       thalamic counts T_t; then all waves stage those senders, issue their
+//       record loads and add the records into rows t .. t+62.
 // ---------------------------------------------------------------------------
 constexpr uint32_t kInline = 4;  // senders carried in a flag word
 
@@ -921,6 +921,20 @@ __device__ __forceinline__ uint32_t sender_gid(const DeviceNet &d, uint32_t j, u
   return w0 + ld_ag(d.llist + size_t(lslot) * d.ntot + w0 + kk);
 }
 
+// Exclusive prefix sum of v over the wave's lanes, and the wave's total: one
+// ballot per bit of v, so the cost grows with the bit length of the largest
+// value, not with the lane count (all lanes active).
+__device__ __forceinline__ uint32_t wave_prefix(uint32_t v, uint32_t &total) {
+  uint32_t p = 0, tot = 0;
+  for (uint32_t b = 0; b < 32u && __ballot(int(v >> b)) != 0ull; ++b) {
+    const uint64_t m = __ballot(int((v >> b) & 1u));
+    p += __builtin_amdgcn_mbcnt_hi(uint32_t(m >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(m), 0u)) << b;
+    tot += uint32_t(__popcll(m)) << b;
+  }
+  total = tot;
+  return p;
+}
+
 // UR record slots per lane.  The wave's senders of a batch are held one per
 // lane (segment address and capacity); their segments are cut into 64-record
 // pieces, numbered sender by sender.  load() takes the next UR pieces, one per
@@ -940,18 +954,9 @@ struct SegmentWalk {
 
   // Lane l holds the segment of the wave's sender l (capacity 0 past the end).
   __device__ __forceinline__ void begin(uint64_t base_lane, uint32_t cap_lane) {
-    const uint32_t lane = __lane_id();
     base_l = base_lane;
     cap_l = cap_lane;
-    const uint32_t n = (cap_lane + 63u) >> 6;
-    uint32_t x = n;   // inclusive scan of the piece counts
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-      const uint32_t y = __shfl_up(x, o);
-      if (lane >= uint32_t(o)) x += y;
-    }
-    p_l = x - n;
-    np = __builtin_amdgcn_readlane(x, 63);
+    p_l = wave_prefix((cap_lane + 63u) >> 6, np);
     p0 = 0;
   }
   __device__ __forceinline__ bool more() const { return p0 < np; }
@@ -962,7 +967,7 @@ struct SegmentWalk {
     for (int u = 0; u < UR; ++u) {
       const uint32_t P = p0 + uint32_t(u);
       // Lanes past the last sender have p_l = np > P, so they never count.
-      const uint32_t s = uint32_t(__popcll(__ballot(p_l <= P))) - 1u;
+      const uint32_t s = uint32_t(__popcll(__ballot(int(p_l <= P)))) - 1u;
       const uint32_t k = P - __builtin_amdgcn_readlane(p_l, s);
       const uint32_t cap = __builtin_amdgcn_readlane(cap_l, s);
       const uint64_t base = ((uint64_t(__builtin_amdgcn_readlane(uint32_t(base_l >> 32), s)) << 32) |
@@ -1010,20 +1015,19 @@ __global__ __launch_bounds__(256) void k_lds(DeviceNet d, uint32_t n_steps, uint
   constexpr uint32_t RC = WN + 128;           // raster staging entries
   constexpr uint32_t SB = BS;                 // senders resolved per batch
   constexpr int UR = 8;                       // record pieces in flight per lane
-  constexpr uint32_t ND = (WN + BS - 1) / BS; // neurons per thread in the thalamic draw
   static_assert(Q0 >= 128, "waves 0 and 1 own no quad");
   __shared__ int32_t s_ring[kRing * WN];
   __shared__ uint32_t s_thr[8 * TS];
   __shared__ uint2 s_meta[8];
-  __shared__ uint32_t s_cf[9], s_cn[9], s_ccap[9];   // sender classes; entry 8: none
-  __shared__ uint64_t s_cbase[9];
+  __shared__ uint32_t s_cf[8], s_cn[8], s_ccap[8];   // sender classes
+  __shared__ uint64_t s_cbase[8];
   __shared__ uint32_t s_wstart[NZ];           // first neuron of each window of the instance
   __shared__ uint32_t s_sid[SB];              // senders of step t-1 (gid or list marker)
   __shared__ uint64_t s_nzf[NZ];
   __shared__ uint32_t s_nzp[NZ];
   __shared__ uint16_t s_nzb[NZ];
   __shared__ uint64_t s_rast[RC];
-  __shared__ uint32_t s_T[NQ];                // T_t of each quad, one byte per neuron
+  __shared__ uint32_t s_T[2 * NQ];            // T_t of each quad by step parity, a byte per neuron
   __shared__ uint32_t s_wave[BS / 64], s_inl[kInline];
   __shared__ uint32_t s_flag, s_n, s_nnz;
   __shared__ unsigned long long s_rbase;
@@ -1052,9 +1056,8 @@ __global__ __launch_bounds__(256) void k_lds(DeviceNet d, uint32_t n_steps, uint
     const uint32_t r = i / WN, c = i % WN;
     s_ring[i] = c < wlen ? d.W[size_t(r) * d.ntot + wb0 + c] : 0;
   }
-  if (tid <= 8u) {   // entry 8: no class (capacity 0)
-    WinClass c{0, 0, 0, 0, 0};
-    if (tid < 8u) c = d.wcls[size_t(blk) * kWinClasses + tid];
+  if (tid < 8u) {
+    const WinClass c = d.wcls[size_t(blk) * kWinClasses + tid];
     s_cf[tid] = c.first;
     s_cn[tid] = c.n;
     s_ccap[tid] = c.cap;
@@ -1069,20 +1072,6 @@ __global__ __launch_bounds__(256) void k_lds(DeviceNet d, uint32_t n_steps, uint
     for (uint32_t kk = 0; kk < TS; ++kk)
       s_thr[off + kk] = kk < m.y ? d.thr[m.x + kk] : 0xFFFFFFFFu;
     s_meta[tid] = make_uint2(off, m.y);
-  }
-
-  // Thalamic draw: thread tid handles window neurons tid + BS i (i < ND);
-  // tmeta byte i = population of that neuron, 0xFF when it is padding.
-  uint32_t tmeta = 0xFFFFFFFFu;
-#pragma unroll
-  for (uint32_t i = 0; i < ND; ++i) {
-    const uint32_t c = tid + BS * i;
-    uint32_t v = 0xFFu;
-    if (c < wlen) {
-      const uint32_t local = wb0 + c - ip->gbase;
-      if (local < ip->n) v = population(ip, local);
-    }
-    tmeta = (tmeta & ~(0xFFu << (8 * i))) | (v << (8 * i));
   }
 
   float U[4] = {0, 0, 0, 0}, I[4] = {0, 0, 0, 0};
@@ -1103,6 +1092,17 @@ __global__ __launch_bounds__(256) void k_lds(DeviceNet d, uint32_t n_steps, uint
   }
   const uint64_t seed = ip->seed;
   __syncthreads();
+  // Sender classes of the window, block-uniform, kept in scalar registers.
+  uint32_t cls_f[8], cls_n[8], cls_cap[8];
+  uint64_t cls_b[8];
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    cls_f[c] = __builtin_amdgcn_readfirstlane(s_cf[c]);
+    cls_n[c] = __builtin_amdgcn_readfirstlane(s_cn[c]);
+    cls_cap[c] = __builtin_amdgcn_readfirstlane(s_ccap[c]);
+    cls_b[c] = (uint64_t(__builtin_amdgcn_readfirstlane(uint32_t(s_cbase[c] >> 32))) << 32) |
+               __builtin_amdgcn_readfirstlane(uint32_t(s_cbase[c]));
+  }
 
   // Flushes the staged raster entries to the device raster.
   uint32_t rn = 0;
@@ -1122,25 +1122,24 @@ __global__ __launch_bounds__(256) void k_lds(DeviceNet d, uint32_t n_steps, uint
     rn = 0;
   };
 
-  // Thalamic counts T_t of this thread's neurons into s_T (byte per neuron);
-  // one Philox block per quad (eqn:ref's background drive, Sec. 2.2).
-  uint32_t lq_base = (wb0 - ip->gbase) / 4;
+  // Thalamic counts T_t into s_T (one byte per neuron), one quad per thread
+  // of waves 1-3 (thread 64 + k draws quad k) and one Philox block per quad
+  // (eqn:ref's background drive, Sec. 2.2).  Wave 0, the polling wave, draws
+  // nothing; the others draw while it waits for the flags.
+  const uint32_t dq = tid - 64u;               // quad drawn by this thread
+  uint32_t dcode = 0;
+  if (tid >= 64u && dq < wlen / 4) dcode = quad_code(ip, (wb0 - ip->gbase) / 4 + dq);
+  const uint32_t lq_draw = (wb0 - ip->gbase) / 4 + dq;
   auto draw_thalamic = [&](uint64_t t) {
+    if (!(dcode >> 12)) return;                // no real neuron (or no quad)
+    const Philox4 x = philox4x32_10(lq_draw, uint32_t(t), uint32_t(t >> 32), kStreamThalamic,
+                                    uint32_t(seed), uint32_t(seed >> 32));
+    uint32_t tp = 0;
 #pragma unroll
-    for (uint32_t i = 0; i < ND; ++i) {
-      const uint32_t mi = (tmeta >> (8 * i)) & 0xFFu;
-      const uint32_t c = tid + BS * i;
-      if (c >= wlen) continue;
-      uint32_t T = 0;
-      if (mi != 0xFFu) {
-        const Philox4 x = philox4x32_10(lq_base + c / 4, uint32_t(t), uint32_t(t >> 32),
-                                        kStreamThalamic, uint32_t(seed), uint32_t(seed >> 32));
-        const uint32_t m = c & 3u;
-        const uint32_t u = m == 0 ? x.v[0] : m == 1 ? x.v[1] : m == 2 ? x.v[2] : x.v[3];
-        T = thalamic_count(s_thr, s_meta[mi], u);
-      }
-      reinterpret_cast<uint8_t *>(s_T)[c] = uint8_t(T);
-    }
+    for (int m = 0; m < 4; ++m)
+      if ((dcode >> (12 + m)) & 1u)
+        tp |= thalamic_count(s_thr, s_meta[(dcode >> (3 * m)) & 7u], x.v[m]) << (8 * m);
+    s_T[(t & 1u) * NQ + dq] = tp;
   };
 
   for (uint32_t it = 0; it <= n_steps; ++it) {
@@ -1163,7 +1162,7 @@ __global__ __launch_bounds__(256) void k_lds(DeviceNet d, uint32_t n_steps, uint
     // (a) complete step t-1 from ring row t-1 and T_{t-1}.
     if (it > 0 && owner) {
       int32_t *row = s_ring + ((t - 1) & (kRing - 1)) * WN + 4 * oq;
-      const uint32_t Tp = s_T[oq];
+      const uint32_t Tp = s_T[((t - 1) & 1u) * NQ + oq];
 #pragma unroll
       for (int m = 0; m < 4; ++m) {
         const int32_t w = row[m];
@@ -1177,7 +1176,9 @@ __global__ __launch_bounds__(256) void k_lds(DeviceNet d, uint32_t n_steps, uint
       }
     }
 
-    // (b) decide step t and publish its senders.
+    // (b) decide step t and publish its senders: raster entries, the window
+    // offsets of the first kInline spikes for the flag word, list entries for
+    // the others, then the flag.
     if (decide) {
       const uint32_t fl = owner ? lif_quad(PC, k, U, I, R) : 0u;
       uint32_t lo, tot;
@@ -1208,9 +1209,11 @@ __global__ __launch_bounds__(256) void k_lds(DeviceNet d, uint32_t n_steps, uint
           ++p;
         }
       }
-      // List entries must be performed before the flag that announces them.
-      if (cnt > kInline) __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
-      __syncthreads();
+      if (cnt) {   // block-uniform
+        // List entries must be performed before the flag that announces them.
+        if (cnt > kInline) __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
+        __syncthreads();
+      }
       // Wave 1 stores the flag: vector memory operations of a wave complete
       // in order, so the polling wave 0 would otherwise wait for the store's
       // acknowledgement before it can read any flag.
@@ -1230,7 +1233,8 @@ __global__ __launch_bounds__(256) void k_lds(DeviceNet d, uint32_t n_steps, uint
       continue;
     }
 
-    // (c) wait for step t-1's flags; collect the windows that have senders.
+    // (c) wave 0 waits for step t-1's flags and stages their senders; waves
+    // 1-3 draw T_t meanwhile.
     if (wave == 0) {
       uint32_t spins = 0;
       bool ok = true;
@@ -1254,6 +1258,8 @@ __global__ __launch_bounds__(256) void k_lds(DeviceNet d, uint32_t n_steps, uint
           break;
         }
       }
+      // Windows with senders, in window order, and their first sender's
+      // number in the step's sender set.
       uint32_t nzc = 0, sc = 0;
 #pragma unroll
       for (int j = 0; j < NJ; ++j) {
@@ -1261,16 +1267,10 @@ __global__ __launch_bounds__(256) void k_lds(DeviceNet d, uint32_t n_steps, uint
         nzc += c ? 1u : 0u;
         sc += c;
       }
-      // inclusive wave scan of (senders << 10 | windows with senders)
-      const uint32_t v = (sc << 10) | nzc;
-      uint32_t x = v;
-#pragma unroll
-      for (int o = 1; o < 64; o <<= 1) {
-        const uint32_t y = __shfl_up(x, o);
-        if (lane >= uint32_t(o)) x += y;
-      }
-      const uint32_t all = __shfl(x, 63);
-      uint32_t pz = (x - v) & 1023u, ps = (x - v) >> 10;
+      uint32_t all_nz, all_s;
+      uint32_t pz = wave_prefix(nzc, all_nz);
+      const uint32_t ps0 = wave_prefix(sc, all_s);
+      uint32_t ps = ps0;
 #pragma unroll
       for (int j = 0; j < NJ; ++j) {
         const uint32_t c = flag_count(fv[j]);
@@ -1284,7 +1284,7 @@ __global__ __launch_bounds__(256) void k_lds(DeviceNet d, uint32_t n_steps, uint
       }
       // The first SB senders, expanded: gid for inline ones, else a list
       // marker (1 << 31 | relative window << 10 | index).
-      ps = (x - v) >> 10;
+      ps = ps0;
 #pragma unroll
       for (int j = 0; j < NJ; ++j) {
         const uint32_t c = flag_count(fv[j]);
@@ -1294,17 +1294,19 @@ __global__ __launch_bounds__(256) void k_lds(DeviceNet d, uint32_t n_steps, uint
                                    : (1u << 31) | (src << 10) | kk;
       }
       if (lane == 0) {
-        s_nnz = all & 1023u;
-        s_n = all >> 10;
+        s_nnz = all_nz;
+        s_n = all_s;
         s_flag = ok ? 1u : 0u;
       }
+    } else if (decide) {
+      draw_thalamic(t);
     }
     __syncthreads();
+
     if (!__builtin_amdgcn_readfirstlane(s_flag)) break;
     const uint32_t n_prev = __builtin_amdgcn_readfirstlane(s_n);
     const uint32_t nnz = __builtin_amdgcn_readfirstlane(s_nnz);
     const uint64_t tsrc = t - 1;
-    bool drawn = !decide;
     for (uint32_t j0 = 0; j0 < n_prev; j0 += SB) {
       // This wave's senders of the batch: j0 + wave + 4 l, one per lane l.
       const uint32_t nb = min(SB, n_prev - j0);
@@ -1314,29 +1316,19 @@ __global__ __launch_bounds__(256) void k_lds(DeviceNet d, uint32_t n_steps, uint
       if (lane < n_l) {
         const uint32_t gid = sender_gid<SB>(d, j0 + wave + 4u * lane, nnz, epp % kSlots, s_sid,
                                             s_nzf, s_nzp, s_nzb, s_wstart, rel.x);
-        uint32_t ci = 8;
 #pragma unroll
         for (int c = 0; c < 8; ++c)
-          if (gid - s_cf[c] < s_cn[c]) ci = uint32_t(c);
-        cap_lane = s_ccap[ci];
-        base_lane = s_cbase[ci] + uint64_t(gid - s_cf[ci]) * cap_lane;
+          if (gid - cls_f[c] < cls_n[c]) {
+            cap_lane = cls_cap[c];
+            base_lane = cls_b[c] + uint64_t(gid - cls_f[c]) * cls_cap[c];
+          }
       }
       SegmentWalk<COMP, UR> sw;
       sw.begin(base_lane, cap_lane);
       while (sw.more()) {
         sw.load(d);
-        if (!drawn) {   // T_t while the first records are in flight
-          // Keeps the draw from being scheduled ahead of the loads.
-          asm volatile("" : "+v"(lq_base) : : "memory");
-          draw_thalamic(t);
-          drawn = true;
-        }
         sw.template apply<WN>(s_ring, tsrc, wb0);
       }
-    }
-    if (!drawn) {
-      draw_thalamic(t);
-      drawn = true;
     }
     __syncthreads();
   }
