@@ -951,6 +951,7 @@ struct SegmentWalk {
   uint32_t p_l;      // lane l: number of the sender's first piece
   uint32_t np;       // pieces of the batch (wave-uniform)
   uint32_t p0;       // next piece
+  uint32_t nv;       // slots filled by the last load()
 
   // Lane l holds the segment of the wave's sender l (capacity 0 past the end).
   __device__ __forceinline__ void begin(uint64_t base_lane, uint32_t cap_lane) {
@@ -966,18 +967,23 @@ struct SegmentWalk {
 #pragma unroll
     for (int u = 0; u < UR; ++u) {
       const uint32_t P = p0 + uint32_t(u);
+      if (P >= np) {   // wave-uniform
+        if (COMP) r4[u] = 0u; else rec[u] = 0ull;
+        continue;
+      }
       // Lanes past the last sender have p_l = np > P, so they never count.
       const uint32_t s = uint32_t(__popcll(__ballot(int(p_l <= P)))) - 1u;
       const uint32_t k = P - __builtin_amdgcn_readlane(p_l, s);
       const uint32_t cap = __builtin_amdgcn_readlane(cap_l, s);
       const uint64_t base = ((uint64_t(__builtin_amdgcn_readlane(uint32_t(base_l >> 32), s)) << 32) |
                              __builtin_amdgcn_readlane(uint32_t(base_l), s)) + 64u * k;
-      const bool ok = P < np && 64u * k + lane < cap;
+      const bool ok = 64u * k + lane < cap;
       if (COMP)
         r4[u] = ok ? __builtin_nontemporal_load(d.rec4 + base + lane) : 0u;
       else
         rec[u] = ok ? __builtin_nontemporal_load(d.rec8 + base + lane) : 0ull;
     }
+    nv = min(np - p0, uint32_t(UR));
     p0 += UR;
   }
 
@@ -985,6 +991,7 @@ struct SegmentWalk {
   __device__ __forceinline__ void apply(int32_t *s_ring, uint64_t t_src, uint32_t wb0) const {
 #pragma unroll
     for (int u = 0; u < UR; ++u) {
+      if (uint32_t(u) >= nv) break;   // wave-uniform
       uint32_t delay, loc;
       int32_t wq;
       if (COMP) {
@@ -1016,7 +1023,7 @@ __global__ __launch_bounds__(256) void k_lds(DeviceNet d, uint32_t n_steps, uint
   constexpr uint32_t SB = BS;                 // senders resolved per batch
   constexpr int UR = 8;                       // record pieces in flight per lane
   static_assert(Q0 >= 128, "waves 0 and 1 own no quad");
-  __shared__ int32_t s_ring[kRing * WN];
+  __shared__ __align__(16) int32_t s_ring[kRing * WN];
   __shared__ uint32_t s_thr[8 * TS];
   __shared__ uint2 s_meta[8];
   __shared__ uint32_t s_cf[8], s_cn[8], s_ccap[8];   // sender classes
@@ -1092,17 +1099,6 @@ __global__ __launch_bounds__(256) void k_lds(DeviceNet d, uint32_t n_steps, uint
   }
   const uint64_t seed = ip->seed;
   __syncthreads();
-  // Sender classes of the window, block-uniform, kept in scalar registers.
-  uint32_t cls_f[8], cls_n[8], cls_cap[8];
-  uint64_t cls_b[8];
-#pragma unroll
-  for (int c = 0; c < 8; ++c) {
-    cls_f[c] = __builtin_amdgcn_readfirstlane(s_cf[c]);
-    cls_n[c] = __builtin_amdgcn_readfirstlane(s_cn[c]);
-    cls_cap[c] = __builtin_amdgcn_readfirstlane(s_ccap[c]);
-    cls_b[c] = (uint64_t(__builtin_amdgcn_readfirstlane(uint32_t(s_cbase[c] >> 32))) << 32) |
-               __builtin_amdgcn_readfirstlane(uint32_t(s_cbase[c]));
-  }
 
   // Flushes the staged raster entries to the device raster.
   uint32_t rn = 0;
@@ -1161,19 +1157,20 @@ __global__ __launch_bounds__(256) void k_lds(DeviceNet d, uint32_t n_steps, uint
 
     // (a) complete step t-1 from ring row t-1 and T_{t-1}.
     if (it > 0 && owner) {
-      int32_t *row = s_ring + ((t - 1) & (kRing - 1)) * WN + 4 * oq;
+      int4 *row = reinterpret_cast<int4 *>(s_ring + ((t - 1) & (kRing - 1)) * WN + 4 * oq);
+      const int4 wv = *row;
+      *row = make_int4(0, 0, 0, 0);
       const uint32_t Tp = s_T[((t - 1) & 1u) * NQ + oq];
+      // Padding neurons receive no records and no thalamic counts, so their
+      // current stays 0 and the update needs no per-neuron test.
+      const int32_t W4[4] = {wv.x, wv.y, wv.z, wv.w};
 #pragma unroll
       for (int m = 0; m < 4; ++m) {
-        const int32_t w = row[m];
-        row[m] = 0;
-        if ((PC >> (12 + m)) & 1u) {
-          const int32_t T = int32_t((Tp >> (8 * m)) & 0xFFu);
-          I[m] = next_current(I[m], T, wext, w, k.p11);
-          c_con += w;
-          c_poi += uint32_t(T);
-        }
+        const int32_t T = int32_t((Tp >> (8 * m)) & 0xFFu);
+        I[m] = next_current(I[m], T, wext, W4[m], k.p11);
       }
+      c_con += int64_t(W4[0]) + W4[1] + W4[2] + W4[3];
+      c_poi += __builtin_amdgcn_sad_u8(Tp, 0u, 0u);
     }
 
     // (b) decide step t and publish its senders: raster entries, the window
@@ -1316,12 +1313,14 @@ __global__ __launch_bounds__(256) void k_lds(DeviceNet d, uint32_t n_steps, uint
       if (lane < n_l) {
         const uint32_t gid = sender_gid<SB>(d, j0 + wave + 4u * lane, nnz, epp % kSlots, s_sid,
                                             s_nzf, s_nzp, s_nzb, s_wstart, rel.x);
+        // Populations are contiguous and in order: the class is the last
+        // non-empty one starting at or before gid.
+        uint32_t ci = 0;
 #pragma unroll
-        for (int c = 0; c < 8; ++c)
-          if (gid - cls_f[c] < cls_n[c]) {
-            cap_lane = cls_cap[c];
-            base_lane = cls_b[c] + uint64_t(gid - cls_f[c]) * cls_cap[c];
-          }
+        for (int c = 1; c < 8; ++c)
+          if (gid >= s_cf[c] && s_cn[c]) ci = uint32_t(c);
+        cap_lane = gid - s_cf[ci] < s_cn[ci] ? s_ccap[ci] : 0u;
+        base_lane = s_cbase[ci] + uint64_t(gid - s_cf[ci]) * cap_lane;
       }
       SegmentWalk<COMP, UR> sw;
       sw.begin(base_lane, cap_lane);
