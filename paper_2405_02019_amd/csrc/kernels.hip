@@ -896,7 +896,7 @@ __device__ __forceinline__ uint32_t flag_local(uint64_t f, uint32_t k) {
 // (s_nzf / s_nzp / s_nzb, relative to window rel0; nnz of them); senders past
 // a window's fourth come from its list in memory.
 template <uint32_t SB>
-__device__ __forceinline__ uint32_t sender_gid(const DeviceNet &d, uint32_t j, uint32_t nnz,
+__device__ __forceinline__ uint32_t sender_gid(const uint32_t *llist, uint32_t ntot, uint32_t j, uint32_t nnz,
                                                uint32_t lslot, const uint32_t *s_sid,
                                                const uint64_t *s_nzf, const uint32_t *s_nzp,
                                                const uint16_t *s_nzb, const uint32_t *s_wstart,
@@ -918,7 +918,7 @@ __device__ __forceinline__ uint32_t sender_gid(const DeviceNet &d, uint32_t j, u
     if (kk < kInline) return s_wstart[src] + flag_local(s_nzf[lo], kk);
   }
   const uint32_t w0 = s_wstart[src];
-  return w0 + ld_ag(d.llist + size_t(lslot) * d.ntot + w0 + kk);
+  return w0 + ld_ag(llist + size_t(lslot) * ntot + w0 + kk);
 }
 
 // Exclusive prefix sum of v over the wave's lanes, and the wave's total: one
@@ -1054,7 +1054,7 @@ __global__ __launch_bounds__(256) void k_lds(DeviceNet d, uint32_t n_steps, uint
   const uint32_t q = wb0 / 4 + oq;
   const bool owner = tid >= Q0 && oq < wlen / 4;
   const InstDev *ip = d.inst + inst;
-  const Props k{d.consts->p11, d.consts->p22, d.consts->p21};
+  const Props k_s{d.consts->p11, d.consts->p22, d.consts->p21};
   const uint2 rel = d.wrel[blk];              // windows whose senders can reach this one
   uint64_t *const flags = d.lflags;
 
@@ -1086,7 +1086,7 @@ __global__ __launch_bounds__(256) void k_lds(DeviceNet d, uint32_t n_steps, uint
   uint32_t OD[4] = {0, 0, 0, 0};
   int64_t c_con = 0;
   uint64_t c_ev = 0;
-  const int32_t wext = ip->w_ext_q;
+  const int32_t wext_s = ip->w_ext_q;
   if (owner) {
     const float4 uv = ld4(d.U + 4 * size_t(q));
     const float4 iv = ld4(d.I + 4 * size_t(q));
@@ -1097,22 +1097,43 @@ __global__ __launch_bounds__(256) void k_lds(DeviceNet d, uint32_t n_steps, uint
     const uint4 od = *reinterpret_cast<const uint4 *>(d.outdeg + 4 * size_t(q));
     OD[0] = od.x; OD[1] = od.y; OD[2] = od.z; OD[3] = od.w;
   }
-  const uint64_t seed = ip->seed;
+  uint64_t seed = ip->seed;
+  uint32_t *llist_v = d.llist;
+  uint64_t *raster_v = d.raster;
+  Control *ctl_v = d.ctl;
+  uint64_t rcap_v = d.raster_cap;
+  uint32_t ntot_v = d.ntot;
+  // Pointers of the rare paths (lists, raster flush, errors) likewise.
+  asm volatile("" : "+v"(llist_v), "+v"(raster_v), "+v"(ctl_v), "+v"(rcap_v), "+v"(ntot_v));
+  // Block-uniform values used only by vector arithmetic live in vector
+  // registers, which are plentiful, and leave scalar registers to the loop.
+  Props k = k_s;
+  int32_t wext = wext_s;
+  uint32_t wb0v = wb0;
+  asm volatile("" : "+v"(seed), "+v"(k.p11), "+v"(k.p22), "+v"(k.p21), "+v"(wext), "+v"(wb0v));
+  // Flag index (window) read by lane l in poll slot j, ~0 past the windows
+  // that can reach this one.
+  uint32_t pb[NJ];
+#pragma unroll
+  for (int j = 0; j < NJ; ++j) {
+    const uint32_t bb = rel.x + lane + 64u * uint32_t(j);
+    pb[j] = bb < rel.y ? bb : ~0u;
+  }
   __syncthreads();
 
   // Flushes the staged raster entries to the device raster.
   uint32_t rn = 0;
   auto flush = [&]() {
     if (tid == 0)
-      s_rbase = atomicAdd(reinterpret_cast<unsigned long long *>(&d.ctl->raster_n),
+      s_rbase = atomicAdd(reinterpret_cast<unsigned long long *>(&ctl_v->raster_n),
                           (unsigned long long)rn);
     __syncthreads();
     for (uint32_t i = tid; i < rn; i += BS) {
       const uint64_t pos = s_rbase + i;
-      if (pos < d.raster_cap)
-        d.raster[pos] = s_rast[i];
+      if (pos < rcap_v)
+        raster_v[pos] = s_rast[i];
       else
-        d.ctl->overflow = 1;
+        ctl_v->overflow = 1;
     }
     __syncthreads();
     rn = 0;
@@ -1149,10 +1170,7 @@ __global__ __launch_bounds__(256) void k_lds(DeviceNet d, uint32_t n_steps, uint
     uint64_t fv[NJ];
     if (wave == 0 && it > 0) {
 #pragma unroll
-      for (int j = 0; j < NJ; ++j) {
-        const uint32_t bb = rel.x + lane + 64u * uint32_t(j);
-        fv[j] = bb < rel.y ? ld_ag(fs + bb) : 0ull;
-      }
+      for (int j = 0; j < NJ; ++j) fv[j] = pb[j] != ~0u ? ld_ag(fs + pb[j]) : 0ull;
     }
 
     // (a) complete step t-1 from ring row t-1 and T_{t-1}.
@@ -1191,7 +1209,7 @@ __global__ __launch_bounds__(256) void k_lds(DeviceNet d, uint32_t n_steps, uint
       }
       if (fl) {
         uint32_t p = before + lo;
-        uint32_t *lst = d.llist + size_t(ep % kSlots) * d.ntot + wb0;
+        uint32_t *lst = llist_v + size_t(ep % kSlots) * ntot_v + wb0;
         c_spk += __popc(fl);
 #pragma unroll
         for (int m = 0; m < 4; ++m) {
@@ -1238,19 +1256,15 @@ __global__ __launch_bounds__(256) void k_lds(DeviceNet d, uint32_t n_steps, uint
       for (;;) {
         bool mine = true;
 #pragma unroll
-        for (int j = 0; j < NJ; ++j) {
-          const uint32_t bb = rel.x + lane + 64u * uint32_t(j);
-          mine = mine && (bb >= rel.y || (uint32_t(fv[j]) & 0xFFFFu) == (epp & 0xFFFFu));
-        }
+        for (int j = 0; j < NJ; ++j)
+          mine = mine && (pb[j] == ~0u || (uint32_t(fv[j]) & 0xFFFFu) == (epp & 0xFFFFu));
         if (__all(mine)) break;
         __builtin_amdgcn_s_sleep(1);
 #pragma unroll
-        for (int j = 0; j < NJ; ++j) {   // reload every flag of the lane: one round trip
-          const uint32_t bb = rel.x + lane + 64u * uint32_t(j);
-          if (bb < rel.y) fv[j] = ld_ag(fs + bb);
-        }
-        if ((++spins & 63u) == 0 && (ld_ag(&d.ctl->error) != 0 || spins > spin_limit)) {
-          if (lane == 0) st_ag(&d.ctl->error, 2u);
+        for (int j = 0; j < NJ; ++j)   // reload every flag of the lane: one round trip
+          if (pb[j] != ~0u) fv[j] = ld_ag(fs + pb[j]);
+        if ((++spins & 63u) == 0 && (ld_ag(&ctl_v->error) != 0 || spins > spin_limit)) {
+          if (lane == 0) st_ag(&ctl_v->error, 2u);
           ok = false;
           break;
         }
@@ -1311,7 +1325,7 @@ __global__ __launch_bounds__(256) void k_lds(DeviceNet d, uint32_t n_steps, uint
       uint64_t base_lane = 0;
       uint32_t cap_lane = 0;
       if (lane < n_l) {
-        const uint32_t gid = sender_gid<SB>(d, j0 + wave + 4u * lane, nnz, epp % kSlots, s_sid,
+        const uint32_t gid = sender_gid<SB>(llist_v, ntot_v, j0 + wave + 4u * lane, nnz, epp % kSlots, s_sid,
                                             s_nzf, s_nzp, s_nzb, s_wstart, rel.x);
         // Populations are contiguous and in order: the class is the last
         // non-empty one starting at or before gid.
@@ -1326,7 +1340,7 @@ __global__ __launch_bounds__(256) void k_lds(DeviceNet d, uint32_t n_steps, uint
       sw.begin(base_lane, cap_lane);
       while (sw.more()) {
         sw.load(d);
-        sw.template apply<WN>(s_ring, tsrc, wb0);
+        sw.template apply<WN>(s_ring, tsrc, wb0v);
       }
     }
     __syncthreads();
