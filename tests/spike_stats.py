@@ -76,3 +76,86 @@ def first_digest_divergence(dig_a, dig_b):
     n = min(len(dig_a), len(dig_b))
     diff = np.flatnonzero(np.any(np.asarray(dig_a[:n]) != np.asarray(dig_b[:n]), axis=1))
     return int(diff[0]) if len(diff) else None
+
+
+# ---------------------------------------------------------------------------
+# Distribution comparison of Sec. 4.1: per population, the distributions of
+# single-neuron firing rates, CVs of inter-spike intervals and Pearson
+# correlation coefficients between binned spike trains of a neuron sample,
+# each smoothed by a Gaussian kernel density estimate (Scott's rule) and
+# compared by the Kullback-Leibler divergence.
+# ---------------------------------------------------------------------------
+
+def neuron_rates(steps, ids, lo, hi, t0, t1):
+    """Firing rate (Hz) of every neuron in [lo, hi) over steps [t0, t1)."""
+    m = (steps >= t0) & (steps < t1) & (ids >= lo) & (ids < hi)
+    return np.bincount(ids[m].astype(np.int64) - lo, minlength=hi - lo) / ((t1 - t0) * DT_S)
+
+
+def neuron_cvs(steps, ids, lo, hi, t0, t1, min_spikes=3):
+    """CV of inter-spike intervals of every neuron in [lo, hi) with at least
+    min_spikes spikes in [t0, t1)."""
+    m = (steps >= t0) & (steps < t1) & (ids >= lo) & (ids < hi)
+    s, i = steps[m].astype(np.int64), ids[m].astype(np.int64)
+    order = np.lexsort((s, i))
+    s, i = s[order], i[order]
+    if len(s) == 0:
+        return np.zeros(0)
+    bounds = np.flatnonzero(np.diff(i)) + 1
+    out = []
+    for a, b in zip(np.concatenate([[0], bounds]), np.concatenate([bounds, [len(i)]])):
+        if b - a >= min_spikes:
+            isi = np.diff(s[a:b]).astype(np.float64)
+            out.append(isi.std() / isi.mean())
+    return np.array(out)
+
+
+def pearson_samples(steps, ids, lo, hi, t0, t1, n_sample=200, bin_steps=20, seed=0):
+    """Pearson correlation coefficients between the binned spike trains
+    (bins of bin_steps steps) of every pair in a sample of n_sample neurons
+    of [lo, hi) drawn with a fixed seed; pairs with a silent neuron excluded."""
+    rng = np.random.default_rng(seed)
+    n = hi - lo
+    sample = np.sort(rng.choice(n, size=min(n_sample, n), replace=False)) + lo
+    nb = (t1 - t0) // bin_steps
+    m = (steps >= t0) & (steps < t0 + nb * bin_steps) & np.isin(ids, sample)
+    row = np.searchsorted(sample, ids[m])
+    col = (steps[m].astype(np.int64) - t0) // bin_steps
+    counts = np.zeros((len(sample), nb))
+    np.add.at(counts, (row, col), 1.0)
+    active = counts.std(axis=1) > 0
+    c = np.corrcoef(counts[active])
+    iu = np.triu_indices(c.shape[0], k=1)
+    return c[iu]
+
+
+def kde_on_grid(samples, grid):
+    """Gaussian kernel density estimate (Scott's rule bandwidth) on a grid,
+    normalised to integrate to one over the grid."""
+    from scipy.stats import gaussian_kde
+    samples = np.asarray(samples, np.float64)
+    if len(samples) < 2 or samples.std() == 0:
+        raise ValueError("need at least two distinct samples")
+    p = gaussian_kde(samples, bw_method="scott")(grid)
+    return p / np.trapezoid(p, grid)
+
+
+def kl_divergence(p, q, grid, floor=1e-12):
+    """KL(P || Q) of two densities on the same grid (trapezoidal rule)."""
+    p = np.maximum(np.asarray(p, np.float64), floor)
+    q = np.maximum(np.asarray(q, np.float64), floor)
+    return float(np.trapezoid(p * np.log(p / q), grid))
+
+
+STAT_NAMES = ("rate", "cv", "pearson")
+
+
+def population_distributions(steps, ids, offsets, t0, t1):
+    """Samples of the three statistics per population."""
+    out = []
+    for p in range(len(offsets) - 1):
+        lo, hi = int(offsets[p]), int(offsets[p + 1])
+        out.append({"rate": neuron_rates(steps, ids, lo, hi, t0, t1),
+                    "cv": neuron_cvs(steps, ids, lo, hi, t0, t1),
+                    "pearson": pearson_samples(steps, ids, lo, hi, t0, t1, seed=p)})
+    return out

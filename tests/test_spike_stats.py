@@ -42,3 +42,32 @@ def test_step_digest_locates_first_difference():
     i2 = i.copy(); i2[3] = 6
     assert first_digest_divergence(d, step_digest(s, i2, 6)) == 3
     assert first_digest_divergence(d, step_digest(s[:4], i[:4], 6)) == 4
+
+
+def test_kde_and_kl_against_closed_forms():
+    from spike_stats import kde_on_grid, kl_divergence
+    rng = np.random.default_rng(1)
+    grid = np.linspace(-8, 10, 4001)
+    a = kde_on_grid(rng.normal(0.0, 1.0, 20000), grid)
+    b = kde_on_grid(rng.normal(1.0, 1.0, 20000), grid)
+    assert abs(np.trapezoid(a, grid) - 1.0) < 1e-9
+    assert kl_divergence(a, a, grid) == 0.0
+    # KL(N(0,1) || N(1,1)) = 1/2; the KDE widens both by the same bandwidth
+    assert abs(kl_divergence(a, b, grid) - 0.5) < 0.06
+
+
+def test_pearson_of_identical_and_independent_trains():
+    from spike_stats import pearson_samples
+    rng = np.random.default_rng(2)
+    steps, ids = [], []
+    base = np.sort(rng.choice(100000, 800, replace=False))
+    for i in range(10):                      # ten copies of one train: r = 1
+        steps.append(base); ids.append(np.full(len(base), i))
+    for i in range(10, 40):                  # independent Poisson trains: r ~ 0
+        s = np.sort(rng.choice(100000, 800, replace=False))
+        steps.append(s); ids.append(np.full(len(s), i))
+    s = np.concatenate(steps); i = np.concatenate(ids)
+    r = pearson_samples(s, i, 0, 10, 0, 100000, n_sample=10)
+    np.testing.assert_allclose(r, 1.0, atol=1e-12)
+    r = pearson_samples(s, i, 10, 40, 0, 100000, n_sample=30)
+    assert abs(r.mean()) < 0.01 and r.std() < 0.05
