@@ -128,6 +128,28 @@ __device__ __forceinline__ uint32_t lif_quad(uint32_t code, Props k, float (&u)[
   return flags;
 }
 
+// lif_quad for quads whose padding neurons hold u = i = 0 and r = 0: such a
+// neuron stays at 0 below the threshold, so every lane updates all four
+// neurons without tests or branches.  Same arithmetic as lif_quad.
+__device__ __forceinline__ uint32_t lif_quad_padded(Props k, float (&u)[4], const float (&i)[4],
+                                                    uint32_t &r4) {
+  uint32_t flags = 0, rout = 0;
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    const uint32_t r = (r4 >> (8 * m)) & 0xFFu;
+    const float a = k.p22 * u[m];
+    const float b = k.p21 * i[m];
+    const float xm = a + b;
+    const bool spike = r == 0 && xm >= kTheta;
+    u[m] = (r == 0 && !spike) ? xm : 0.0f;
+    const uint32_t rn = spike ? kRefSteps : (r ? r - 1u : 0u);
+    flags |= uint32_t(spike) << m;
+    rout |= rn << (8 * m);
+  }
+  r4 = rout;
+  return flags;
+}
+
 // Step t of a quad: the thalamic counts T_t (packed one byte per neuron into
 // tp, their sum added to tsum) and the membrane update.  tab/meta hold the
 // thalamic tables; meta[mbase + population] = (offset, length).
@@ -1195,7 +1217,7 @@ __global__ __launch_bounds__(256) void k_lds(DeviceNet d, uint32_t n_steps, uint
     // offsets of the first kInline spikes for the flag word, list entries for
     // the others, then the flag.
     if (decide) {
-      const uint32_t fl = owner ? lif_quad(PC, k, U, I, R) : 0u;
+      const uint32_t fl = owner ? lif_quad_padded(k, U, I, R) : 0u;
       uint32_t lo, tot;
       wave_compact(fl, lo, tot);
       if (lane == 0) s_wave[wave] = tot;
