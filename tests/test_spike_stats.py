@@ -71,3 +71,19 @@ def test_pearson_of_identical_and_independent_trains():
     np.testing.assert_allclose(r, 1.0, atol=1e-12)
     r = pearson_samples(s, i, 10, 40, 0, 100000, n_sample=30)
     assert abs(r.mean()) < 0.01 and r.std() < 0.05
+
+
+def test_kde_bandwidth_is_scotts_rule():
+    """A Gaussian KDE is a mixture of N(x_i, h^2): its variance is the sample
+    variance plus h^2, with Scott's h^2 = n^(-2/5) times the unbiased sample
+    variance in one dimension."""
+    from spike_stats import kde_on_grid
+    rng = np.random.default_rng(3)
+    x = rng.gamma(2.0, 1.0, 500)
+    grid = np.linspace(x.min() - 10, x.max() + 10, 20001)
+    p = kde_on_grid(x, grid)
+    mean = np.trapezoid(p * grid, grid)
+    var = np.trapezoid(p * (grid - mean) ** 2, grid)
+    expect = x.var() + len(x) ** -0.4 * x.var(ddof=1)
+    assert abs(mean - x.mean()) < 1e-6
+    assert abs(var / expect - 1.0) < 1e-5
