@@ -1120,26 +1120,27 @@ __global__ __launch_bounds__(256) void k_lds(DeviceNet d, uint32_t n_steps, uint
     OD[0] = od.x; OD[1] = od.y; OD[2] = od.z; OD[3] = od.w;
   }
   uint64_t seed = ip->seed;
-  uint32_t *llist_v = d.llist;
-  uint64_t *raster_v = d.raster;
-  Control *ctl_v = d.ctl;
-  uint64_t rcap_v = d.raster_cap;
-  uint32_t ntot_v = d.ntot;
-  // Pointers of the rare paths (lists, raster flush, errors) likewise.
-  asm volatile("" : "+v"(llist_v), "+v"(raster_v), "+v"(ctl_v), "+v"(rcap_v), "+v"(ntot_v));
   // Block-uniform values used only by vector arithmetic live in vector
   // registers, which are plentiful, and leave scalar registers to the loop.
   Props k = k_s;
   int32_t wext = wext_s;
   uint32_t wb0v = wb0;
   asm volatile("" : "+v"(seed), "+v"(k.p11), "+v"(k.p22), "+v"(k.p21), "+v"(wext), "+v"(wb0v));
+  // Pointers of the rare paths (lists, raster flush, errors) likewise.
+  uint32_t *llist_v = d.llist;
+  uint64_t *raster_v = d.raster;
+  Control *ctl_v = d.ctl;
+  uint64_t rcap_v = d.raster_cap;
+  uint32_t ntot_v = d.ntot;
+  asm volatile("" : "+v"(llist_v), "+v"(raster_v), "+v"(ctl_v), "+v"(rcap_v), "+v"(ntot_v));
   // Flag index (window) read by lane l in poll slot j, ~0 past the windows
-  // that can reach this one.
-  uint32_t pb[NJ];
+  // that can reach this one, and that window's first neuron.
+  uint32_t pb[NJ], wst[NJ];
 #pragma unroll
   for (int j = 0; j < NJ; ++j) {
     const uint32_t bb = rel.x + lane + 64u * uint32_t(j);
     pb[j] = bb < rel.y ? bb : ~0u;
+    wst[j] = bb < rel.y ? d.lwin[bb].x : 0u;
   }
   __syncthreads();
 
@@ -1291,39 +1292,41 @@ __global__ __launch_bounds__(256) void k_lds(DeviceNet d, uint32_t n_steps, uint
           break;
         }
       }
-      // Windows with senders, in window order, and their first sender's
-      // number in the step's sender set.
-      uint32_t nzc = 0, sc = 0;
+      // Number of each lane's first sender in the step's sender set.
+      uint32_t sc = 0;
 #pragma unroll
-      for (int j = 0; j < NJ; ++j) {
-        const uint32_t c = flag_count(fv[j]);
-        nzc += c ? 1u : 0u;
-        sc += c;
-      }
-      uint32_t all_nz, all_s;
-      uint32_t pz = wave_prefix(nzc, all_nz);
+      for (int j = 0; j < NJ; ++j) sc += flag_count(fv[j]);
+      uint32_t all_s, all_nz = 0;
       const uint32_t ps0 = wave_prefix(sc, all_s);
-      uint32_t ps = ps0;
+      if (all_s > SB) {   // wave-uniform
+        // Senders past the first SB are found by search over the windows
+        // with senders, in window order, with their first sender's number.
+        uint32_t nzc = 0;
 #pragma unroll
-      for (int j = 0; j < NJ; ++j) {
-        const uint32_t c = flag_count(fv[j]);
-        if (c) {
-          s_nzf[pz] = fv[j];
-          s_nzp[pz] = ps;
-          s_nzb[pz] = uint16_t(lane + 64u * uint32_t(j));   // window, relative to rel.x
-          ++pz;
-          ps += c;
+        for (int j = 0; j < NJ; ++j) nzc += flag_count(fv[j]) ? 1u : 0u;
+        uint32_t pz = wave_prefix(nzc, all_nz);
+        uint32_t ps = ps0;
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) {
+          const uint32_t c = flag_count(fv[j]);
+          if (c) {
+            s_nzf[pz] = fv[j];
+            s_nzp[pz] = ps;
+            s_nzb[pz] = uint16_t(lane + 64u * uint32_t(j));   // window, relative to rel.x
+            ++pz;
+            ps += c;
+          }
         }
       }
       // The first SB senders, expanded: gid for inline ones, else a list
       // marker (1 << 31 | relative window << 10 | index).
-      ps = ps0;
+      uint32_t ps = ps0;
 #pragma unroll
       for (int j = 0; j < NJ; ++j) {
         const uint32_t c = flag_count(fv[j]);
         const uint32_t src = lane + 64u * uint32_t(j);
         for (uint32_t kk = 0; kk < c && ps < SB; ++kk, ++ps)
-          s_sid[ps] = kk < kInline ? s_wstart[src] + flag_local(fv[j], kk)
+          s_sid[ps] = kk < kInline ? wst[j] + flag_local(fv[j], kk)
                                    : (1u << 31) | (src << 10) | kk;
       }
       if (lane == 0) {
