@@ -1046,7 +1046,7 @@ __global__ __launch_bounds__(256) void k_lds(DeviceNet d, uint32_t n_steps, uint
   constexpr int UR = 8;                       // record pieces in flight per lane
   static_assert(Q0 >= 128, "waves 0 and 1 own no quad");
   __shared__ __align__(16) int32_t s_ring[kRing * WN];
-  __shared__ uint32_t s_thr[8 * TS];
+  __shared__ __align__(16) uint32_t s_thr[8 * TS];
   __shared__ uint2 s_meta[8];
   __shared__ uint32_t s_cf[8], s_cn[8], s_ccap[8];   // sender classes
   __shared__ uint64_t s_cbase[8];
@@ -1174,11 +1174,33 @@ __global__ __launch_bounds__(256) void k_lds(DeviceNet d, uint32_t n_steps, uint
     if (!(dcode >> 12)) return;                // no real neuron (or no quad)
     const Philox4 x = philox4x32_10(lq_draw, uint32_t(t), uint32_t(t >> 32), kStreamThalamic,
                                     uint32_t(seed), uint32_t(seed >> 32));
+    // All table reads first (16 bytes at a time, population p's table at
+    // p TS), then the counts without branches; a count reaching 8 continues
+    // in the table (rare).
+    uint4 lo[4], hi[4];
+    uint32_t len[4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const uint32_t pm = (dcode >> (3 * m)) & 7u;
+      const uint4 *tb = reinterpret_cast<const uint4 *>(s_thr + pm * TS);
+      lo[m] = tb[0];
+      hi[m] = tb[1];
+      len[m] = s_meta[pm].y;
+    }
     uint32_t tp = 0;
 #pragma unroll
-    for (int m = 0; m < 4; ++m)
-      if ((dcode >> (12 + m)) & 1u)
-        tp |= thalamic_count(s_thr, s_meta[(dcode >> (3 * m)) & 7u], x.v[m]) << (8 * m);
+    for (int m = 0; m < 4; ++m) {
+      const uint32_t u = x.v[m], L = len[m];
+      const uint32_t v[8] = {lo[m].x, lo[m].y, lo[m].z, lo[m].w, hi[m].x, hi[m].y, hi[m].z, hi[m].w};
+      uint32_t T = 0;
+#pragma unroll
+      for (uint32_t kk = 0; kk < 8; ++kk) T += (kk < L && u >= v[kk]) ? 1u : 0u;
+      if (T == 8u) {
+        const uint32_t *tab = s_thr + ((dcode >> (3 * m)) & 7u) * TS;
+        while (T < L && u >= tab[T]) ++T;
+      }
+      tp |= (((dcode >> (12 + m)) & 1u) ? T : 0u) << (8 * m);
+    }
     s_T[(t & 1u) * NQ + dq] = tp;
   };
 
