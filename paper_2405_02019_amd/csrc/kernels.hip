@@ -1187,20 +1187,29 @@ __global__ __launch_bounds__(256) void k_lds(DeviceNet d, uint32_t n_steps, uint
       hi[m] = tb[1];
       len[m] = s_meta[pm].y;
     }
-    uint32_t tp = 0;
+    // Table entries past a table's length hold ~0, which no word below ~0
+    // reaches; the word ~0 reaches every entry, so its count is the length.
+    uint32_t T[4];
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
-      const uint32_t u = x.v[m], L = len[m];
+      const uint32_t u = x.v[m];
       const uint32_t v[8] = {lo[m].x, lo[m].y, lo[m].z, lo[m].w, hi[m].x, hi[m].y, hi[m].z, hi[m].w};
-      uint32_t T = 0;
+      uint32_t c = 0;
 #pragma unroll
-      for (uint32_t kk = 0; kk < 8; ++kk) T += (kk < L && u >= v[kk]) ? 1u : 0u;
-      if (T == 8u) {
-        const uint32_t *tab = s_thr + ((dcode >> (3 * m)) & 7u) * TS;
-        while (T < L && u >= tab[T]) ++T;
-      }
-      tp |= (((dcode >> (12 + m)) & 1u) ? T : 0u) << (8 * m);
+      for (int kk = 0; kk < 8; ++kk) c += u >= v[kk] ? 1u : 0u;
+      T[m] = u == ~0u ? len[m] : c;
     }
+    if (T[0] == 8u || T[1] == 8u || T[2] == 8u || T[3] == 8u) {   // rare
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        const uint32_t *tab = s_thr + ((dcode >> (3 * m)) & 7u) * TS;
+        if (T[m] == 8u)
+          while (T[m] < len[m] && x.v[m] >= tab[T[m]]) ++T[m];
+      }
+    }
+    uint32_t tp = 0;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) tp |= (((dcode >> (12 + m)) & 1u) ? T[m] : 0u) << (8 * m);
     s_T[(t & 1u) * NQ + dq] = tp;
   };
 
