@@ -1057,6 +1057,7 @@ __global__ __launch_bounds__(256) void k_lds(DeviceNet d, uint32_t n_steps, uint
   __shared__ uint16_t s_nzb[NZ];
   __shared__ uint64_t s_rast[RC];
   __shared__ uint32_t s_T[2 * NQ];            // T_t of each quad by step parity, a byte per neuron
+  __shared__ uint4 s_px[NQ];                  // Philox words of each quad for T_t
   __shared__ uint32_t s_wave[BS / 64], s_inl[kInline];
   __shared__ uint32_t s_flag, s_n, s_nnz;
   __shared__ unsigned long long s_rbase;
@@ -1162,18 +1163,27 @@ __global__ __launch_bounds__(256) void k_lds(DeviceNet d, uint32_t n_steps, uint
     rn = 0;
   };
 
-  // Thalamic counts T_t into s_T (one byte per neuron), one quad per thread
-  // of waves 1-3 (thread 64 + k draws quad k) and one Philox block per quad
-  // (eqn:ref's background drive, Sec. 2.2).  Wave 0, the polling wave, draws
-  // nothing; the others draw while it waits for the flags.
-  const uint32_t dq = tid - 64u;               // quad drawn by this thread
-  uint32_t dcode = 0;
-  if (tid >= 64u && dq < wlen / 4) dcode = quad_code(ip, (wb0 - ip->gbase) / 4 + dq);
-  const uint32_t lq_draw = (wb0 - ip->gbase) / 4 + dq;
-  auto draw_thalamic = [&](uint64_t t) {
-    if (!(dcode >> 12)) return;                // no real neuron (or no quad)
-    const Philox4 x = philox4x32_10(lq_draw, uint32_t(t), uint32_t(t >> 32), kStreamThalamic,
+  // Thalamic counts T_t into s_T (one byte per neuron), one Philox block per
+  // quad (eqn:ref's background drive, Sec. 2.2), in two parts placed where
+  // waves are idle: waves 0 and 1 (no quads) compute the Philox words of quad
+  // tid while the owners complete and decide the step (draw_words); waves 1-3
+  // turn the words of quad tid - 64 into counts while wave 0 waits for the
+  // flags (draw_counts).
+  const uint32_t lq0 = (wb0 - ip->gbase) / 4;
+  const uint32_t nq_win = wlen / 4;
+  auto draw_words = [&](uint64_t t) {
+    if (tid >= 128u || tid >= nq_win) return;
+    const Philox4 x = philox4x32_10(lq0 + tid, uint32_t(t), uint32_t(t >> 32), kStreamThalamic,
                                     uint32_t(seed), uint32_t(seed >> 32));
+    s_px[tid] = make_uint4(x.v[0], x.v[1], x.v[2], x.v[3]);
+  };
+  const uint32_t dq = tid - 64u;               // quad counted by this thread
+  uint32_t dcode = 0;
+  if (tid >= 64u && dq < nq_win) dcode = quad_code(ip, lq0 + dq);
+  auto draw_counts = [&](uint64_t t) {
+    if (!(dcode >> 12)) return;                // no real neuron (or no quad)
+    const uint4 xw = s_px[dq];
+    const Philox4 x{{xw.x, xw.y, xw.z, xw.w}};
     // All table reads first (16 bytes at a time, population p's table at
     // p TS), then the counts without branches; a count reaching 8 continues
     // in the table (rare).
@@ -1226,6 +1236,7 @@ __global__ __launch_bounds__(256) void k_lds(DeviceNet d, uint32_t n_steps, uint
 #pragma unroll
       for (int j = 0; j < NJ; ++j) fv[j] = pb[j] != ~0u ? ld_ag(fs + pb[j]) : 0ull;
     }
+    if (decide) draw_words(t);   // waves 0 and 1
 
     // (a) complete step t-1 from ring row t-1 and T_{t-1}.
     if (it > 0 && owner) {
@@ -1297,7 +1308,7 @@ __global__ __launch_bounds__(256) void k_lds(DeviceNet d, uint32_t n_steps, uint
     }
 
     if (it == 0) {   // nothing to deliver yet
-      draw_thalamic(t);
+      draw_counts(t);
       __syncthreads();
       continue;
     }
@@ -1366,7 +1377,7 @@ __global__ __launch_bounds__(256) void k_lds(DeviceNet d, uint32_t n_steps, uint
         s_flag = ok ? 1u : 0u;
       }
     } else if (decide) {
-      draw_thalamic(t);
+      draw_counts(t);
     }
     __syncthreads();
 
