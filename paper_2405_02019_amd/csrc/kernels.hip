@@ -900,9 +900,10 @@ hipError_t launch_persistent(const DeviceNet &d, const LaunchShape &sh, uint32_t
 // Iteration it (t = t0 + it):
 //   (a) complete step t-1 from ring row t-1 and the thalamic counts T_{t-1};
 //   (b) decide step t (membrane update only) and publish its flag;
-//   (c) wave 0 waits for the flags of step t-1 while waves 1-3 draw the
-//       thalamic counts T_t; then all waves stage those senders, issue their
-//       record loads and add the records into rows t .. t+62.
+//   (c) waves 0 and 3 wait for the flags of step t-1 (half of the windows
+//       each) while waves 1 and 2 finish the thalamic counts T_t; then all
+//       waves stage those senders, issue their record loads and add the
+//       records into rows t .. t+62.
 // ---------------------------------------------------------------------------
 constexpr uint32_t kInline = 4;  // senders carried in a flag word
 
@@ -1040,9 +1041,11 @@ __global__ __launch_bounds__(256) void k_lds(DeviceNet d, uint32_t n_steps, uint
   constexpr uint32_t Q0 = BS - NQ;            // threads Q0.. own one quad each
   constexpr uint32_t TS = kLdsTab + 8;        // stride of an LDS thalamic table
   constexpr uint32_t NZ = kLdsMaxGrid;        // windows of one instance, at most
-  constexpr int NJ = NZ / 64;                 // flags per lane of the polling wave
+  constexpr int NJ = NZ / 128;                // flags per lane of a polling wave
+  constexpr uint32_t NZH = NZ / 2;            // windows polled by one wave
   constexpr uint32_t RC = WN + 128;           // raster staging entries
   constexpr uint32_t SB = BS;                 // senders resolved per batch
+  constexpr uint32_t SBH = SB / 2;            // senders staged per polling wave
   constexpr int UR = 8;                       // record pieces in flight per lane
   static_assert(Q0 >= 128, "waves 0 and 1 own no quad");
   __shared__ __align__(16) int32_t s_ring[kRing * WN];
@@ -1059,7 +1062,7 @@ __global__ __launch_bounds__(256) void k_lds(DeviceNet d, uint32_t n_steps, uint
   __shared__ uint32_t s_T[2 * NQ];            // T_t of each quad by step parity, a byte per neuron
   __shared__ uint4 s_px[NQ];                  // Philox words of each quad for T_t
   __shared__ uint32_t s_wave[BS / 64], s_inl[kInline];
-  __shared__ uint32_t s_flag, s_n, s_nnz;
+  __shared__ uint32_t s_flag[2], s_n[2], s_nnz[2];   // per polling wave
   __shared__ unsigned long long s_rbase;
   __shared__ long long s_ctr[4];
 
@@ -1134,12 +1137,16 @@ __global__ __launch_bounds__(256) void k_lds(DeviceNet d, uint32_t n_steps, uint
   uint64_t rcap_v = d.raster_cap;
   uint32_t ntot_v = d.ntot;
   asm volatile("" : "+v"(llist_v), "+v"(raster_v), "+v"(ctl_v), "+v"(rcap_v), "+v"(ntot_v));
-  // Flag index (window) read by lane l in poll slot j, ~0 past the windows
-  // that can reach this one, and that window's first neuron.
+  // Waves 0 and 3 poll the flags: wave 0 of the first NZH windows that can
+  // reach this one (h = 0), wave 3 of the others (h = 1).  Flag index
+  // (window) read by lane l in poll slot j, ~0 past the windows that can
+  // reach this one, and that window's first neuron.
+  const bool poller = wave == 0 || wave == 3;
+  const uint32_t h = wave == 3 ? 1u : 0u;
   uint32_t pb[NJ], wst[NJ];
 #pragma unroll
   for (int j = 0; j < NJ; ++j) {
-    const uint32_t bb = rel.x + lane + 64u * uint32_t(j);
+    const uint32_t bb = rel.x + NZH * h + lane + 64u * uint32_t(j);
     pb[j] = bb < rel.y ? bb : ~0u;
     wst[j] = bb < rel.y ? d.lwin[bb].x : 0u;
   }
@@ -1166,9 +1173,9 @@ __global__ __launch_bounds__(256) void k_lds(DeviceNet d, uint32_t n_steps, uint
   // Thalamic counts T_t into s_T (one byte per neuron), one Philox block per
   // quad (eqn:ref's background drive, Sec. 2.2), in two parts placed where
   // waves are idle: waves 0 and 1 (no quads) compute the Philox words of quad
-  // tid while the owners complete and decide the step (draw_words); waves 1-3
-  // turn the words of quad tid - 64 into counts while wave 0 waits for the
-  // flags (draw_counts).
+  // tid while the owners complete and decide the step (draw_words); threads
+  // 64 + k of waves 1 and 2 turn the words of quad k into counts while waves
+  // 0 and 3 wait for the flags (draw_counts).
   const uint32_t lq0 = (wb0 - ip->gbase) / 4;
   const uint32_t nq_win = wlen / 4;
   auto draw_words = [&](uint64_t t) {
@@ -1230,9 +1237,10 @@ __global__ __launch_bounds__(256) void k_lds(DeviceNet d, uint32_t n_steps, uint
     const uint32_t epp = ep - 1;              // epoch of step t-1's flags
     const uint64_t *fs = flags + size_t(epp % kSlots) * GT;
 
-    // Wave 0 issues the flag loads of step t-1 now; they are checked in (c).
+    // The polling waves issue the flag loads of step t-1 now; they are
+    // checked in (c).
     uint64_t fv[NJ];
-    if (wave == 0 && it > 0) {
+    if (poller && it > 0) {
 #pragma unroll
       for (int j = 0; j < NJ; ++j) fv[j] = pb[j] != ~0u ? ld_ag(fs + pb[j]) : 0ull;
     }
@@ -1313,9 +1321,9 @@ __global__ __launch_bounds__(256) void k_lds(DeviceNet d, uint32_t n_steps, uint
       continue;
     }
 
-    // (c) wave 0 waits for step t-1's flags and stages their senders; waves
-    // 1-3 draw T_t meanwhile.
-    if (wave == 0) {
+    // (c) waves 0 and 3 wait for step t-1's flags of their windows and stage
+    // their senders; waves 1 and 2 draw T_t meanwhile.
+    if (poller) {
       uint32_t spins = 0;
       bool ok = true;
       for (;;) {
@@ -1334,14 +1342,15 @@ __global__ __launch_bounds__(256) void k_lds(DeviceNet d, uint32_t n_steps, uint
           break;
         }
       }
-      // Number of each lane's first sender in the step's sender set.
+      // Number of each lane's first sender in this wave's sender set.
       uint32_t sc = 0;
 #pragma unroll
       for (int j = 0; j < NJ; ++j) sc += flag_count(fv[j]);
       uint32_t all_s, all_nz = 0;
       const uint32_t ps0 = wave_prefix(sc, all_s);
-      if (all_s > SB) {   // wave-uniform
-        // Senders past the first SB are found by search over the windows
+      uint32_t *const sid = s_sid + SBH * h;
+      if (all_s > SBH) {   // wave-uniform
+        // Senders past the first SBH are found by search over the windows
         // with senders, in window order, with their first sender's number.
         uint32_t nzc = 0;
 #pragma unroll
@@ -1352,38 +1361,38 @@ __global__ __launch_bounds__(256) void k_lds(DeviceNet d, uint32_t n_steps, uint
         for (int j = 0; j < NJ; ++j) {
           const uint32_t c = flag_count(fv[j]);
           if (c) {
-            s_nzf[pz] = fv[j];
-            s_nzp[pz] = ps;
-            s_nzb[pz] = uint16_t(lane + 64u * uint32_t(j));   // window, relative to rel.x
+            s_nzf[NZH * h + pz] = fv[j];
+            s_nzp[NZH * h + pz] = ps;
+            s_nzb[NZH * h + pz] = uint16_t(NZH * h + lane + 64u * uint32_t(j));   // window, relative to rel.x
             ++pz;
             ps += c;
           }
         }
       }
-      // The first SB senders, expanded: gid for inline ones, else a list
+      // The first SBH senders, expanded: gid for inline ones, else a list
       // marker (1 << 31 | relative window << 10 | index).
       uint32_t ps = ps0;
 #pragma unroll
       for (int j = 0; j < NJ; ++j) {
         const uint32_t c = flag_count(fv[j]);
-        const uint32_t src = lane + 64u * uint32_t(j);
-        for (uint32_t kk = 0; kk < c && ps < SB; ++kk, ++ps)
-          s_sid[ps] = kk < kInline ? wst[j] + flag_local(fv[j], kk)
-                                   : (1u << 31) | (src << 10) | kk;
+        const uint32_t src = NZH * h + lane + 64u * uint32_t(j);
+        for (uint32_t kk = 0; kk < c && ps < SBH; ++kk, ++ps)
+          sid[ps] = kk < kInline ? wst[j] + flag_local(fv[j], kk)
+                                 : (1u << 31) | (src << 10) | kk;
       }
       if (lane == 0) {
-        s_nnz = all_nz;
-        s_n = all_s;
-        s_flag = ok ? 1u : 0u;
+        s_nnz[h] = all_nz;
+        s_n[h] = all_s;
+        s_flag[h] = ok ? 1u : 0u;
       }
     } else if (decide) {
       draw_counts(t);
     }
     __syncthreads();
 
-    if (!__builtin_amdgcn_readfirstlane(s_flag)) break;
-    const uint32_t n_prev = __builtin_amdgcn_readfirstlane(s_n);
-    const uint32_t nnz = __builtin_amdgcn_readfirstlane(s_nnz);
+    if (!__builtin_amdgcn_readfirstlane(s_flag[0] & s_flag[1])) break;
+    const uint32_t n0 = __builtin_amdgcn_readfirstlane(s_n[0]);
+    const uint32_t n_prev = n0 + __builtin_amdgcn_readfirstlane(s_n[1]);
     const uint64_t tsrc = t - 1;
     for (uint32_t j0 = 0; j0 < n_prev; j0 += SB) {
       // This wave's senders of the batch: j0 + wave + 4 l, one per lane l.
@@ -1392,8 +1401,12 @@ __global__ __launch_bounds__(256) void k_lds(DeviceNet d, uint32_t n_steps, uint
       uint64_t base_lane = 0;
       uint32_t cap_lane = 0;
       if (lane < n_l) {
-        const uint32_t gid = sender_gid<SB>(llist_v, ntot_v, j0 + wave + 4u * lane, nnz, epp % kSlots, s_sid,
-                                            s_nzf, s_nzp, s_nzb, s_wstart, rel.x);
+        // Senders of polling wave 0 come first, then those of wave 3.
+        const uint32_t j = j0 + wave + 4u * lane;
+        const uint32_t hs = j < n0 ? 0u : 1u;
+        const uint32_t gid = sender_gid<SBH>(llist_v, ntot_v, j - (hs ? n0 : 0u), s_nnz[hs], epp % kSlots,
+                                             s_sid + SBH * hs, s_nzf + NZH * hs, s_nzp + NZH * hs,
+                                             s_nzb + NZH * hs, s_wstart, rel.x);
         // Populations are contiguous and in order: the class is the last
         // non-empty one starting at or before gid.
         uint32_t ci = 0;
