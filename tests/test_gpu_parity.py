@@ -131,6 +131,28 @@ def test_lds_windows(P, oracle, grid, fmt, wmode):
         assert_parity(sim, 0, net, osim)
 
 
+@pytest.mark.parametrize("fmt,wmode", [("plain", 0), ("compressed", 1)])
+def test_lds_high_activity(P, oracle, fmt, wmode):
+    """LDS engine under a burst: the half-scale circuit with weak inhibition
+    (g = -2) and a 16 Hz background opens with steps of several hundred
+    spikes.  Covers windows with more than four spikes in a step (list
+    entries), more senders in a step than a polling wave stages (search
+    over the windows with senders), both polling waves (more than 128
+    windows) and senders whose segments span several pieces."""
+    inst = P.Instance(scale=0.5, seed=7, g=-2.0, bg_rate_hz=16.0)
+    say("lds high activity", fmt)
+    with P.Simulator(inst, syn_format=fmt, engine="lds", chunk_steps=50) as sim:
+        info = sim.info()
+        assert info["engine"] == P.ENGINE_LDS and info["grid_blocks"] > 128
+        sim.step(150)
+        net, osim = run_oracle(oracle, inst, wmode, 150)
+        steps, _ = osim.raster()
+        per_step = np.bincount(steps, minlength=150)
+        say("spikes per step: max", per_step.max(), "mean", per_step.mean())
+        assert per_step.max() > 2 * 128
+        assert_parity(sim, 0, net, osim)
+
+
 def test_degenerate_drives(P, oracle):
     """No synapses and no thalamic input; then a constant count of one
     thalamic spike per step at a sub-threshold amplitude; then no drive at
