@@ -193,7 +193,7 @@ def main():
         print(msg, file=sys.stderr, flush=True)
 
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only: this build simulates one microcircuit (or one batch) "
+        print(f"bench.py runs on one GPU only: the simulator runs one microcircuit (or one batch) "
               f"per device and has no multi-GPU path; got --gpus {args.gpus}", file=sys.stderr)
         sys.exit(2)
     if int(os.environ.get("WORLD_SIZE", "1")) > 1:

@@ -10,7 +10,8 @@
  *    [target][source]); a flag swaps the orientation.
  *  - Synapse counts follow the microcircuit's fixed-total-number rule,
  *    n = ln(1-p) / ln(1 - 1/(N_pre N_post)) rounded half up, which gives the
- *    "around 300 million" synapses of Sec. 2.2 (N_pre N_post p gives 2.85e8).
+ *    full-scale total of about 3e8 synapses stated in Sec. 2.2 (N_pre N_post p
+ *    gives 2.85e8).
  *    log1p evaluates both logarithms without cancellation.
  *  - Each synapse draws its sender and receiver uniformly with replacement,
  *    so multapses and autapses occur (Sec. 2.1.1, Sec. 2.2).
