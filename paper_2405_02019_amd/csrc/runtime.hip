@@ -42,6 +42,8 @@ struct snn_net {
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;
   std::vector<uint64_t> raster;     // drained; sorted by (step, global id) up to raster_sorted
+  uint64_t *staging = nullptr;      // pinned host buffer for raster drains
+  size_t staging_cap = 0;           // its capacity in entries
   size_t raster_sorted = 0;         // later drains hold later steps: only the tail needs sorting
   uint64_t t = 0;
   uint64_t pending = 0;             // worst-case raster entries since the last drain
@@ -108,6 +110,9 @@ void release(snn_net *h) {
       (void)hipFree(p);
   }
   h->allocs.clear();
+  if (h->staging) (void)hipHostFree(h->staging);
+  h->staging = nullptr;
+  h->staging_cap = 0;
   if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
   h->stream = nullptr;
 }
@@ -124,12 +129,21 @@ int drain(snn_net *h) {
   if (c.overflow) h->overflowed = true;
   const uint64_t m = std::min<uint64_t>(c.raster_n, h->d.raster_cap);
   if (m) {
-    const size_t old = h->raster.size();
-    h->raster.resize(old + m);
-    HIP_OK(h, hipMemcpy(h->raster.data() + old, h->d.raster, m * sizeof(uint64_t),
-                        hipMemcpyDeviceToHost));
+    // Through a pinned buffer: a copy into pageable memory is staged by the
+    // runtime in small pieces.
+    if (m > h->staging_cap) {
+      if (h->staging) (void)hipHostFree(h->staging);
+      h->staging = nullptr;
+      h->staging_cap = 0;
+      const size_t cap = std::max<size_t>(m, size_t(1) << 18);
+      HIP_OK(h, hipHostMalloc(reinterpret_cast<void **>(&h->staging), cap * sizeof(uint64_t),
+                              hipHostMallocDefault));
+      h->staging_cap = cap;
+    }
+    HIP_OK(h, hipMemcpy(h->staging, h->d.raster, m * sizeof(uint64_t), hipMemcpyDeviceToHost));
+    h->raster.insert(h->raster.end(), h->staging, h->staging + m);
   }
-  HIP_OK(h, launch_reset_raster(h->d, h->stream));
+  if (c.raster_n || c.overflow) HIP_OK(h, launch_reset_raster(h->d, h->stream));
   h->pending = 0;
   return SNN_OK;
 }
@@ -161,6 +175,61 @@ void sort_raster_tail(std::vector<uint64_t> &r, size_t from) {
     a = start[k];
   }
   std::copy(out.begin(), out.end(), r.begin() + from);
+}
+
+// The LDS engine's raster: a block stages its spikes in (step, id) order and
+// flushes them as one contiguous run, and blocks own disjoint windows of ids
+// in window order.  Taking the runs window by window (drain order within a
+// window), a stable counting sort by step leaves every step's ids ascending
+// with no sort within steps.  Returns false where a comparison sort is the
+// better choice (entries sparse in time).
+bool sort_raster_tail_windows(std::vector<uint64_t> &r, size_t from,
+                              const std::vector<InstMeta> &im) {
+  const size_t n = r.size() - from;
+  if (n < 2) return true;
+  uint64_t lo = ~0ull, hi = 0;
+  for (size_t i = from; i < r.size(); ++i) {
+    lo = std::min(lo, r[i] >> 32);
+    hi = std::max(hi, r[i] >> 32);
+  }
+  const uint64_t span = hi - lo + 1;
+  if (span > 4 * n + 1024) return false;
+  const uint32_t nwin = im.back().win0 + im.back().nwin;
+  auto window_of = [&](uint32_t g) {
+    size_t a = 0, b = im.size();   // last instance with gbase <= g
+    while (b - a > 1) {
+      const size_t c = (a + b) / 2;
+      if (im[c].gbase <= g) a = c; else b = c;
+    }
+    return im[a].win0 + (g - im[a].gbase) / im[a].wlen;
+  };
+  std::vector<uint32_t> run_at, run_win;   // runs of one window: first entry, window
+  uint32_t prev = ~0u;
+  for (size_t i = 0; i < n; ++i) {
+    const uint32_t w = window_of(uint32_t(r[from + i]));
+    if (w != prev) {
+      run_at.push_back(uint32_t(i));
+      run_win.push_back(w);
+      prev = w;
+    }
+  }
+  const size_t nruns = run_at.size();
+  run_at.push_back(uint32_t(n));
+  std::vector<uint32_t> first(size_t(nwin) + 1, 0), order(nruns);
+  for (size_t k = 0; k < nruns; ++k) ++first[run_win[k] + 1];
+  for (uint32_t w = 0; w < nwin; ++w) first[w + 1] += first[w];
+  for (size_t k = 0; k < nruns; ++k) order[first[run_win[k]]++] = uint32_t(k);
+  std::vector<uint32_t> at(span + 1, 0);
+  for (size_t i = from; i < r.size(); ++i) ++at[(r[i] >> 32) - lo + 1];
+  for (uint64_t k = 0; k < span; ++k) at[k + 1] += at[k];
+  std::vector<uint64_t> out(n);
+  for (const uint32_t k : order)
+    for (uint32_t i = run_at[k]; i < run_at[k + 1]; ++i) {
+      const uint64_t v = r[from + i];
+      out[at[(v >> 32) - lo]++] = v;
+    }
+  std::copy(out.begin(), out.end(), r.begin() + from);
+  return true;
 }
 
 uint64_t spike_bound(const snn_net *h, uint64_t steps) {
@@ -762,7 +831,8 @@ int snn_read_spikes(snn_net *h, uint32_t inst, uint64_t t0, uint64_t t1, uint32_
   t0 = std::min<uint64_t>(t0, 0xFFFFFFFFull);
   t1 = std::min<uint64_t>(t1, 0x100000000ull);
   if (h->raster_sorted < h->raster.size()) {
-    sort_raster_tail(h->raster, h->raster_sorted);
+    if (h->engine != SNN_ENGINE_LDS || !sort_raster_tail_windows(h->raster, h->raster_sorted, h->im))
+      sort_raster_tail(h->raster, h->raster_sorted);
     h->raster_sorted = h->raster.size();
   }
   auto lo = std::lower_bound(h->raster.begin(), h->raster.end(), t0 << 32);
