@@ -232,6 +232,14 @@ bool sort_raster_tail_windows(std::vector<uint64_t> &r, size_t from,
   return true;
 }
 
+// Orders the raster entries drained since the last call.
+void sort_drained(snn_net *h) {
+  if (h->raster_sorted >= h->raster.size()) return;
+  if (h->engine != SNN_ENGINE_LDS || !sort_raster_tail_windows(h->raster, h->raster_sorted, h->im))
+    sort_raster_tail(h->raster, h->raster_sorted);
+  h->raster_sorted = h->raster.size();
+}
+
 uint64_t spike_bound(const snn_net *h, uint64_t steps) {
   // A neuron spikes at most once per 21 steps (20 refractory steps).
   return h->n_real * ((steps + kRefSteps) / (kRefSteps + 1));
@@ -816,6 +824,7 @@ int snn_step_n(snn_net *h, uint64_t n_steps) {
     h->pending += spike_bound(h, piece);
     h->t += piece;
     n_steps -= piece;
+    sort_drained(h);   // while the device runs the chunk just queued
   }
   return SNN_OK;
 }
@@ -830,11 +839,7 @@ int snn_read_spikes(snn_net *h, uint32_t inst, uint64_t t0, uint64_t t1, uint32_
   const InstMeta &m = h->im[inst];
   t0 = std::min<uint64_t>(t0, 0xFFFFFFFFull);
   t1 = std::min<uint64_t>(t1, 0x100000000ull);
-  if (h->raster_sorted < h->raster.size()) {
-    if (h->engine != SNN_ENGINE_LDS || !sort_raster_tail_windows(h->raster, h->raster_sorted, h->im))
-      sort_raster_tail(h->raster, h->raster_sorted);
-    h->raster_sorted = h->raster.size();
-  }
+  sort_drained(h);
   auto lo = std::lower_bound(h->raster.begin(), h->raster.end(), t0 << 32);
   auto hi = t1 >= 0x100000000ull ? h->raster.end()
                                  : std::lower_bound(h->raster.begin(), h->raster.end(), t1 << 32);
