@@ -180,7 +180,7 @@ def main():
                     help="timed seconds of biological time (default: 10 full, 2 batch, 5 x4)")
     ap.add_argument("--warmup", type=int, default=1, help="untimed seconds of biological time")
     ap.add_argument("--engine", default="auto", choices=["auto", "stepwise", "persistent", "lds"])
-    ap.add_argument("--chunk", type=int, default=1000, help="simulation steps per launch (chunk)")
+    ap.add_argument("--chunk", type=int, default=10000, help="simulation steps per launch (chunk)")
     ap.add_argument("--no-compressed", action="store_true", help="skip the compressed-synapse leg")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain-synapse leg")
     ap.add_argument("--cpu-steps", type=int, default=4000,
