@@ -183,7 +183,7 @@ def main():
     ap.add_argument("--chunk", type=int, default=10000, help="simulation steps per launch (chunk)")
     ap.add_argument("--no-compressed", action="store_true", help="skip the compressed-synapse leg")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain-synapse leg")
-    ap.add_argument("--cpu-steps", type=int, default=4000,
+    ap.add_argument("--cpu-steps", type=int, default=10000,
                     help="oracle steps for the CPU baseline, full workload only (0 = skip)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run the 1 GiB copy used to scale HBM counters")
