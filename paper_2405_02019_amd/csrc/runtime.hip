@@ -844,9 +844,13 @@ int snn_read_spikes(snn_net *h, uint32_t inst, uint64_t t0, uint64_t t1, uint32_
   auto hi = t1 >= 0x100000000ull ? h->raster.end()
                                  : std::lower_bound(h->raster.begin(), h->raster.end(), t1 << 32);
   uint64_t cnt = 0;
-  for (auto it = lo; it < hi; ++it) {
-    const uint32_t g = uint32_t(*it);
-    cnt += (g >= m.gbase && g < m.gbase + m.n);
+  if (h->im.size() == 1) {   // every entry is the one instance's
+    cnt = uint64_t(hi - lo);
+  } else {
+    for (auto it = lo; it < hi; ++it) {
+      const uint32_t g = uint32_t(*it);
+      cnt += (g >= m.gbase && g < m.gbase + m.n);
+    }
   }
   *n_out = cnt;
   if (!steps && !ids) return SNN_OK;
