@@ -7,18 +7,20 @@ the paper's RTF).  The timed region runs from the first step launch to the
 read-back of the timed window's spike rasters, bracketed by
 torch.cuda.synchronize(); networks are built and uploaded before it.
 
-Workloads (--workload):
+Workloads (--workload selects the headline one):
   full   the full-scale circuit, 77,169 neurons, ~3e8 synapses; plain and
          compressed legs; defaults 1 warm-up + 10 timed seconds (the paper's
          10 s runs).  The default.
   batch  64 independent instances of uneven scale (5-20 %), g and background
-         rate; compressed and plain legs; 2 timed seconds.
+         rate, compressed synapses; 2 timed seconds.
   x4     four times the neurons, full in-degrees (308,676 neurons, ~1.2e9
          synapses); plain and compressed legs; 5 timed seconds.
+With the full workload as the headline, the batch and x4 workloads run too
+(unless --no-extra) and are reported under "workloads".
 
 Reported value: synaptic events per second (device-counted activations of
 synapses by spikes) of the first leg over the timed region.  The line also
-carries the real-time factor, the other leg, the roofline of the dominant
+carries the real-time factor, the other legs, the roofline of the dominant
 kernel (timed live with HIP events on the library's stream) and, for the
 full workload, the CPU oracle's throughput on a bounded sample.
 """
@@ -37,13 +39,14 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, 8 TB/s
 WORKLOADS = {
     "full": {"legs": ["plain", "compressed"], "steps": 10,
              "name": "full-scale PD microcircuit, 77,169 neurons, {syn} synapses, dt 0.1 ms"},
-    "batch": {"legs": ["compressed", "plain"], "steps": 2,
+    "batch": {"legs": ["compressed"], "steps": 2,
               "name": "64 independent PD instances, scale U[5%,20%], g U[-6,-3], background "
                       "U[6,10] Hz, full in-degrees; {neurons} neurons, {syn} synapses, dt 0.1 ms"},
     "x4": {"legs": ["plain", "compressed"], "steps": 5,
            "name": "4x PD microcircuit with full in-degrees, {neurons} neurons, {syn} synapses, "
                    "dt 0.1 ms"},
 }
+KERNEL_SOURCES = {"k_lds": "kernels.hip", "k_persistent": "kernels.hip", "k_band": "band.hip"}
 
 
 def algorithmic_bytes(n_neurons, spikes, events, rec_bytes):
@@ -61,12 +64,13 @@ def run_leg(P, instances, fmt, engine, chunk, warm_bio_s, timed_bio_s, log):
     info = sim.info()
     log(f"[bench] {fmt}: built in {build_s:.1f} s ({info['n_synapses_total']} synapses, "
         f"engine {info['engine']}, block {info['block_size']}, grid {info['grid_blocks']}, "
+        f"window {info['window_neurons']}, ring rows {info['ring_rows']}, "
         f"launches/chunk {info['launches_per_chunk']}, graphs {info['graphs']})")
     if warm_bio_s:
         sim.step(int(warm_bio_s * STEPS_PER_BIO_SECOND))
     tune = None
-    if info["engine"] != P.ENGINE_LDS:   # the LDS engine's shape is fixed by its layout
-        tune = sim.autotune(500)
+    if info["engine"] in (P.ENGINE_PERSISTENT, P.ENGINE_STEPWISE):   # the LDS engines' shape
+        tune = sim.autotune(500)                                     # is fixed by their layout
         info = sim.info()
         log(f"[bench] {fmt}: autotuned over {tune['candidates']} shapes: block {tune['block_size']}, "
             f"grid {tune['grid_blocks']}, quads/thread {tune['quads_per_thread']}, "
@@ -74,6 +78,7 @@ def run_leg(P, instances, fmt, engine, chunk, warm_bio_s, timed_bio_s, log):
     ni = len(instances)
     s0 = [sim.state(i) for i in range(ni)]
     t0_step = s0[0]["t"]
+    sim.discard_spikes(t0_step)
     n_steps = int(timed_bio_s * STEPS_PER_BIO_SECOND)
     torch.cuda.synchronize()
     w0 = time.perf_counter()
@@ -89,11 +94,11 @@ def run_leg(P, instances, fmt, engine, chunk, warm_bio_s, timed_bio_s, log):
     spikes = sum(b["spikes"] - a["spikes"] for a, b in zip(s0, s1))
     assert spikes == n_raster, (spikes, n_raster)
     n = sum(b["n_neurons"] for b in s1)
-    lds = info["engine"] == P.ENGINE_LDS
-    rec = 8.0 if fmt == "plain" else (4.0 if lds else 5.0)
+    windowed = info["engine"] in (P.ENGINE_LDS, P.ENGINE_BAND)
+    rec = 8.0 if fmt == "plain" else (4.0 if windowed else 5.0)
     ring_b, syn_b = algorithmic_bytes(n, spikes, events, rec)
     total_bytes = ring_b * n_steps + syn_b
-    chunked = info["engine"] in (P.ENGINE_PERSISTENT, P.ENGINE_LDS)
+    chunked = info["engine"] in (P.ENGINE_PERSISTENT, P.ENGINE_LDS, P.ENGINE_BAND)
     launches = (-(-n_steps // info["chunk_steps"]) * info["launches_per_chunk"] if chunked
                 else 2 * n_steps)
     sim.close()
@@ -109,26 +114,58 @@ def kernel_name(P, info):
     e = info["engine"]
     if e == P.ENGINE_LDS:
         return "k_lds"
+    if e == P.ENGINE_BAND:
+        return "k_band"
     if e == P.ENGINE_PERSISTENT:
         return "k_persistent"
     return "k_update + k_transfer"
 
 
-def measured_traffic(kernel, workload, fmt, chunk):
-    """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE
-    summary, scaled by the copy calibration -- only while the kernel source is
-    the one the counters were taken on, for the same chunk length."""
+def profile_record(kernel, workload, fmt, chunk):
+    """The committed rocprofv3 counter summary of a kernel and workload
+    (profiles/traffic_<kernel>_<workload>_<fmt>.json) -- only while the
+    kernel's source is the one the counters were taken on, for the same
+    launch length."""
     import hashlib
     path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}_{fmt}.json")
-    if not os.path.exists(path):
+    if not os.path.exists(path) or kernel not in KERNEL_SOURCES:
         return None
     rec = json.load(open(path))
-    src = os.path.join(ROOT, "paper_2405_02019_amd", "csrc", "kernels.hip")
+    src = os.path.join(ROOT, "paper_2405_02019_amd", "csrc", KERNEL_SOURCES[kernel])
     if hashlib.sha256(open(src, "rb").read()).hexdigest() != rec["kernel_source_sha256"]:
         return None
     if rec.get("chunk_steps") != chunk:
         return None
-    return rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]
+    return rec
+
+
+def roofline(P, leg, workload):
+    avg_launch_ms = leg["gpu_ms"] / leg["launches"]
+    achieved = leg["bytes"] / leg["launches"] / (avg_launch_ms * 1e-3) / 1e9
+    kname = kernel_name(P, leg["info"])
+    kernel = kname
+    if leg["info"]["engine"] in (P.ENGINE_PERSISTENT, P.ENGINE_LDS, P.ENGINE_BAND):
+        kernel += " (cooperative launches of %d steps)" % leg["info"]["chunk_steps"]
+    rec = profile_record(kname, workload, leg["fmt"], leg["info"]["chunk_steps"])
+    out = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": achieved / HBM_PEAK_GBS,
+           "traffic": (rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]) if rec else None,
+           "kernel": kernel, "avg_launch_ms": avg_launch_ms,
+           "bytes_per_launch": leg["bytes"] / leg["launches"]}
+    if rec and "cache" in rec:
+        out["cache"] = rec["cache"]
+    return out
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def cpu_baseline(n_steps, log):
@@ -146,7 +183,8 @@ def cpu_baseline(n_steps, log):
     return {"value": c["events"] / wall, "unit": "synaptic events/s", "cores": 1, "kind": "oracle",
             "sample": f"full-scale microcircuit (77,169 neurons, {net.nsyn} synapses), steps 0-{n_steps} "
                       f"({n_steps / STEPS_PER_BIO_SECOND:.2f} s bio) of the same seed, "
-                      f"{c['events']} events in {wall:.1f} s",
+                      f"{c['events']} events in {wall:.1f} s, one thread",
+            "cpu_model": cpu_model(), "host_cpus": os.cpu_count(),
             "rtf": wall / (n_steps / STEPS_PER_BIO_SECOND)}
 
 
@@ -162,14 +200,29 @@ def copy_calibration(log):
     log("[bench] copied 3 x 1 GiB")
 
 
-def leg_summary(leg, bio):
+def leg_summary(P, leg, bio, workload):
+    info = leg["info"]
     return {"value": leg["events"] / leg["wall_s"], "unit": "synaptic events/s",
             "rtf": leg["wall_s"] / bio, "ms_per_step": 1000.0 * leg["wall_s"] / bio,
             "us_per_sim_step_gpu": 1000.0 * leg["gpu_ms"] / leg["n_steps"],
             "spikes_per_step": leg["spikes"] / leg["n_steps"],
+            "events_per_step": leg["events"] / leg["n_steps"],
             "syn_format": "plain8" if leg["fmt"] == "plain" else "compressed",
             "record_bytes": leg["rec_bytes"], "build_s": leg["build_s"],
-            "device_bytes": leg["info"]["device_bytes"]}
+            "device_bytes": info["device_bytes"], "engine": info["engine"],
+            "block": info["block_size"], "grid": info["grid_blocks"],
+            "window_neurons": info["window_neurons"], "ring_rows": info["ring_rows"],
+            "roofline": roofline(P, leg, workload)}
+
+
+def run_workload(P, workloads, name, args, log, bio_steps=None):
+    wl = WORKLOADS[name]
+    bio = bio_steps if bio_steps is not None else wl["steps"]
+    instances = workloads.WORKLOADS[name]()
+    legs = [f for f in wl["legs"] if not (f == "compressed" and args.no_compressed)
+            and not (f == "plain" and args.no_plain)] or wl["legs"][:1]
+    return bio, instances, [run_leg(P, instances, f, args.engine, args.chunk, args.warmup, bio, log)
+                            for f in legs]
 
 
 def main():
@@ -179,10 +232,12 @@ def main():
     ap.add_argument("--steps", type=int, default=None,
                     help="timed seconds of biological time (default: 10 full, 2 batch, 5 x4)")
     ap.add_argument("--warmup", type=int, default=1, help="untimed seconds of biological time")
-    ap.add_argument("--engine", default="auto", choices=["auto", "stepwise", "persistent", "lds"])
+    ap.add_argument("--engine", default="auto", choices=["auto", "stepwise", "persistent", "lds", "band"])
     ap.add_argument("--chunk", type=int, default=10000, help="simulation steps per launch (chunk)")
-    ap.add_argument("--no-compressed", action="store_true", help="skip the compressed-synapse leg")
-    ap.add_argument("--no-plain", action="store_true", help="skip the plain-synapse leg")
+    ap.add_argument("--no-compressed", action="store_true", help="skip the compressed-synapse legs")
+    ap.add_argument("--no-plain", action="store_true", help="skip the plain-synapse legs")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="with the full workload: skip the batch and x4 workloads")
     ap.add_argument("--cpu-steps", type=int, default=10000,
                     help="oracle steps for the CPU baseline, full workload only (0 = skip)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -209,22 +264,11 @@ def main():
     import paper_2405_02019_amd as P
     from paper_2405_02019_amd import workloads
 
-    wl = WORKLOADS[args.workload]
-    bio_steps = args.steps if args.steps is not None else wl["steps"]
-    instances = workloads.WORKLOADS[args.workload]()
-    legs = [f for f in wl["legs"] if not (f == "compressed" and args.no_compressed)
-            and not (f == "plain" and args.no_plain)]
-    results = [run_leg(P, instances, f, args.engine, args.chunk, args.warmup, bio_steps, log)
-               for f in legs]
+    bio_steps, instances, results = run_workload(P, workloads, args.workload, args, log, args.steps)
     first = results[0]
     bio = float(bio_steps)
-    avg_launch_ms = first["gpu_ms"] / first["launches"]
-    achieved = first["bytes"] / first["launches"] / (avg_launch_ms * 1e-3) / 1e9
-    kname = kernel_name(P, first["info"])
-    kernel = kname
-    if first["info"]["engine"] in (P.ENGINE_PERSISTENT, P.ENGINE_LDS):
-        kernel += " (cooperative launches of %d steps)" % first["info"]["chunk_steps"]
     info = first["info"]
+    wl = WORKLOADS[args.workload]
     out = {
         "metric": "realtime factor & synaptic events/s, full PD microcircuit; plain vs compressed",
         "value": first["events"] / first["wall_s"],
@@ -244,29 +288,34 @@ def main():
                    "syn_format": "plain8" if first["fmt"] == "plain" else "compressed",
                    "instances": len(instances), "engine": info["engine"],
                    "block": info["block_size"], "grid": info["grid_blocks"],
-                   "window_neurons": info["window_neurons"], "chunk_steps": info["chunk_steps"],
+                   "window_neurons": info["window_neurons"], "ring_rows": info["ring_rows"],
+                   "chunk_steps": info["chunk_steps"],
                    "launches_per_chunk": info["launches_per_chunk"], "graphs": info["graphs"],
                    "autotuned": first["tune"] is not None},
         "rtf": first["wall_s"] / bio,
         "bio_per_wall": bio / first["wall_s"],
         "spikes_per_step": first["spikes"] / first["n_steps"],
         "events_per_step": first["events"] / first["n_steps"],
+        "us_per_sim_step_gpu": 1000.0 * first["gpu_ms"] / first["n_steps"],
         "gpu_ms_timed": first["gpu_ms"],
         "build_s": first["build_s"],
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic(kname, args.workload, first["fmt"],
-                                                 info["chunk_steps"]),
-                     "kernel": kernel,
-                     "avg_launch_ms": avg_launch_ms,
-                     "bytes_per_launch": first["bytes"] / first["launches"]},
+        "roofline": roofline(P, first, args.workload),
         "paper_context": {"fpga_rtf_gmem_mono_s": 4.79, "fpga_rtf_best_horiz_multi": 0.79,
                           "hardware": "1 Intel Agilex 7 FPGA (numbers quoted from the paper)"},
     }
     for leg in results[1:]:
-        out[leg["fmt"]] = leg_summary(leg, bio)
+        out[leg["fmt"]] = leg_summary(P, leg, bio, args.workload)
     if args.workload == "full" and args.cpu_steps > 0:
         out["cpu_baseline"] = cpu_baseline(args.cpu_steps, log)
+    if args.workload == "full" and not args.no_extra:
+        out["workloads"] = {}
+        for name in ["batch", "x4"]:
+            wbio, winst, wres = run_workload(P, workloads, name, args, log)
+            out["workloads"][name] = {
+                "workload": WORKLOADS[name]["name"].format(syn=wres[0]["info"]["n_synapses_total"],
+                                                           neurons=wres[0]["n_neurons"]),
+                "instances": len(winst), "timed_bio_s": wbio,
+                "legs": {leg["fmt"]: leg_summary(P, leg, float(wbio), name) for leg in wres}}
     print(json.dumps(out), flush=True)
 
 

@@ -55,20 +55,28 @@ enum snn_syn_format {
   SNN_SYN_PLAIN8 = 0,
   /* 5 bytes in three streams: uint16 target offset inside a 65,536-neuron
      target block, int16 weight in 2^-5 pA, uint8 delay; sorted by sender,
-     then target block (the 16-bit weights of Sec. 5.1). */
+     then target block (the 16-bit weights of Sec. 5.3). */
   SNN_SYN_COMPRESSED5 = 1
 };
 
 /* Step-loop engines. */
 enum snn_engine {
-  SNN_ENGINE_AUTO = 0,        /* LDS when it fits, else persistent, else stepwise */
+  SNN_ENGINE_AUTO = 0,        /* LDS when it fits, else banded, else persistent,
+                                 else stepwise                                    */
   SNN_ENGINE_STEPWISE = 1,    /* two kernels per step (update, then transfer)    */
   SNN_ENGINE_PERSISTENT = 2,  /* one cooperative kernel per chunk of steps, one
                                  grid-wide barrier per step, ring in HBM          */
-  SNN_ENGINE_LDS = 3          /* persistent, each block owning 256 or 512 neurons
+  SNN_ENGINE_LDS = 3,         /* persistent, each block owning 256 or 512 neurons
                                  and their 64 ring rows in LDS; synapses stored
                                  per (sender, destination block); needs the whole
                                  network to fit the co-resident blocks            */
+  SNN_ENGINE_BAND = 4         /* persistent, each block owning up to 3,584 neurons
+                                 and H = 64, 16 or 8 rows of their ring in LDS:
+                                 horizon-based transfer (Sec. 3.4, lst:horizon2)
+                                 with synapses stored per (sender, destination
+                                 block, delay band); the one-step delays are
+                                 delivered first, the other bands while blocks
+                                 wait for each other's spikes                     */
 };
 
 /* One microcircuit instance.  Defaults (snn_instance_default) are the
@@ -145,13 +153,29 @@ int snn_step_n(snn_net *h, uint64_t n_steps);
 
 /*
  * snn_read_spikes -- spikes of instance `inst` emitted in steps [t0, t1),
- * sorted by (step, neuron id).  steps[k], ids[k] receive at most `cap`
- * entries; *n_out is the number of spikes in the range.  Synchronises.
+ * sorted by (step, neuron id).  A spike of step t is a neuron whose membrane
+ * update of step t crossed the threshold (eqn:mem, eqn:ref): the neurons
+ * lst:push2 collects in its queue Q at step t, i.e. the senders whose
+ * synapses that step's transfer activates.  Ids are instance-local
+ * (population p holds [pop_offset[p], pop_offset[p+1]) in table order).
+ * steps[k], ids[k] receive at most `cap` entries (either pointer may be NULL
+ * to skip it; both NULL only counts); *n_out is the number of spikes in the
+ * range.  Spikes discarded by snn_discard_spikes are no longer returned.
+ * Synchronises.
  * Errors: SNN_E_INVAL, SNN_E_RANGE (cap < *n_out; nothing written),
  * SNN_E_OVERFLOW (the device raster overflowed), SNN_E_HIP.
  */
 int snn_read_spikes(snn_net *h, uint32_t inst, uint64_t t0, uint64_t t1, uint32_t *steps,
                     uint32_t *ids, uint64_t cap, uint64_t *n_out);
+
+/*
+ * snn_discard_spikes -- drop the host-side record of every spike (all
+ * instances) of steps before t_before, so that long runs keep a bounded
+ * raster store; later reads of those steps return nothing.  Synchronises
+ * (drains the device raster first).
+ * Errors: SNN_E_INVAL (NULL handle), SNN_E_HIP, SNN_E_DEVICE.
+ */
+int snn_discard_spikes(snn_net *h, uint64_t t_before);
 
 /* State of one instance.  Array pointers are caller buffers (or NULL to
  * skip): U, I, R hold n_neurons entries; W holds 64 * n_neurons entries,
@@ -176,6 +200,16 @@ typedef struct {
 /*
  * snn_read_state -- copy the state of instance `inst` (after the last queued
  * step) into the caller's buffers.  Synchronises.
+ *   U, I, R are the neuron state of eqn:mem, eqn:psc and eqn:ref after step
+ *   t-1: U the membrane potential, I the synaptic current that step t's
+ *   membrane update reads (it already holds the thalamic and ring input of
+ *   step t-1), R the refractory steps left.  W is the wrap-around ring
+ *   buffer of Sec. 3.2 (64 rows, row (s mod 64) collects the input read at
+ *   step s) holding every delivery of every spike emitted so far, in int32
+ *   units of 2^-8 pA.  The counters are exact: spikes, synapse activations
+ *   (each spike activates its sender's out-degree), thalamic events and the
+ *   int64 sum of ring values read (charge conservation: consumed + sum of W
+ *   equals the sum of w_q over all activations).
  * Errors: SNN_E_INVAL, SNN_E_HIP.
  */
 int snn_read_state(snn_net *h, uint32_t inst, snn_state *out);
@@ -201,7 +235,8 @@ typedef struct {
   uint32_t launches_per_chunk; /* kernel launches one chunk of steps takes    */
   uint32_t window_neurons; /* LDS engine: neurons of the longest window      */
   uint32_t graphs;         /* 1: full chunks replay from a captured hipGraph */
-  uint32_t reserved;
+  uint32_t ring_rows;      /* ring-buffer rows kept on chip (LDS engines), or
+                              the 64 rows in device memory                    */
 } snn_info;
 
 int snn_get_info(const snn_net *h, snn_info *out);
@@ -271,6 +306,20 @@ int snn_sample_network(const snn_instance_cfg *inst, uint32_t syn_format, int32_
  */
 int snn_sample_network_windows(const snn_instance_cfg *inst, uint32_t syn_format, uint32_t window,
                                int32_t host_threads, snn_host_network **out);
+/*
+ * snn_sample_network_bands -- as snn_sample_network_windows, but stored in
+ * the layout of the banded engine: `window`-neuron target windows (4 ..
+ * 4,096, a multiple of 4), and per (sender, window) one fixed-capacity
+ * segment per delay band of a ring of `ring_rows` rows (64, 32, 16 or 8):
+ * band 0 holds delay 1, band j >= 1 the delays [2 + (j-1) H, 1 + j H]
+ * (Sec. 3.4's horizon bands, Sec. 3.5's index by sender and delay), read
+ * back into rows ordered by window, then band.  A synapse of weight 0 is
+ * stored like an unused slot and is not read back.
+ * Errors: SNN_E_INVAL for another window or ring size; as
+ * snn_sample_network otherwise.
+ */
+int snn_sample_network_bands(const snn_instance_cfg *inst, uint32_t syn_format, uint32_t window,
+                             uint32_t ring_rows, int32_t host_threads, snn_host_network **out);
 void snn_free_network(snn_host_network *net);
 
 #ifdef __cplusplus

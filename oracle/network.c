@@ -214,7 +214,7 @@ int orc_build(const orc_config *c, orc_net **out) {
   free(g_pre); free(g_post); free(g_d); free(g_w);
 
   /* Fixed-point weights: 2^-8 pA (plain), or int16 in 2^-5 pA scaled to the
-   * same 2^-8 pA accumulator (compressed, Sec. 5.1's 16-bit weights). */
+   * same 2^-8 pA accumulator (compressed, Sec. 5.3's 16-bit weights). */
   for (uint64_t e = 0; e < S; ++e) {
     double w = n->w[e];
     if (c->weight_mode == ORC_W_PLAIN) {

@@ -20,7 +20,7 @@
  *   - push delivery into a wrap-around ring ...... Sec. 3.1-3.2 (lst:push,
  *                                                  lst:push2, D_MAX = 64)
  *   - synapse storage sorted by sender ........... Sec. 3.5 (lst:index)
- *   - 16-bit weights ............................. Sec. 5.1 (Future Research)
+ *   - 16-bit weights ............................. Sec. 5.3 (Future Research)
  *
  * Readings taken where the paper is silent or ambiguous are listed in the
  * project's design notes; each is restated next to the code it affects.

@@ -20,7 +20,7 @@ HIP_FLAGS = ["-O3", "-std=c++17", "-fPIC", "-ffp-contract=off", "-fno-gpu-flush-
              f"--offload-arch={ARCH}", "-Wall", "-Wno-unused-result"]
 CXX_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-ffp-contract=off", "-fno-fast-math", "-pthread",
              "-Wall", "-Wextra"]
-HIP_SOURCES = ["kernels.hip", "runtime.hip"]
+HIP_SOURCES = ["kernels.hip", "band.hip", "runtime.hip"]
 CXX_SOURCES = ["model.cpp", "builder.cpp"]
 
 
@@ -31,16 +31,20 @@ def _run(cmd, verbose):
 
 
 def build(verbose=False):
+    from concurrent.futures import ThreadPoolExecutor
     os.makedirs(OUT, exist_ok=True)
-    objs = []
+    jobs = []
     for src in HIP_SOURCES:
         obj = os.path.join(OUT, src.replace(".hip", ".o"))
-        _run(["hipcc", *HIP_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj], verbose)
-        objs.append(obj)
+        jobs.append((["hipcc", *HIP_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj], obj))
     for src in CXX_SOURCES:
         obj = os.path.join(OUT, src.replace(".cpp", ".o"))
-        _run(["g++", *CXX_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj], verbose)
-        objs.append(obj)
+        jobs.append((["g++", *CXX_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj], obj))
+    # The translation units compile independently, the largest first.
+    with ThreadPoolExecutor(max_workers=min(len(jobs), os.cpu_count() or 1)) as ex:
+        for f in [ex.submit(_run, cmd, verbose) for cmd, _ in jobs]:
+            f.result()
+    objs = [obj for _, obj in jobs]
     tmp = LIB + ".tmp"
     _run(["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", "-pthread", "-o", tmp, *objs],
          verbose)

@@ -86,9 +86,14 @@ uint32_t thalamic_table_max(const snn_instance_cfg &cfg) {
   return m;
 }
 
-int sample_instance(const snn_instance_cfg &cfg, uint32_t syn_format, uint32_t win_size,
-                    uint32_t win_origin, bool pad, int threads, HostInstance &out,
-                    std::string &err) {
+namespace {
+
+// Everything of an instance but its synapses: populations, pair counts,
+// weights of the thalamic drive and its count tables, initial potentials,
+// and the population pairs in generation order (target-major).
+int prepare_instance(const snn_instance_cfg &cfg, uint32_t syn_format, int &threads,
+                     HostInstance &out, std::vector<Pair> &pairs, uint32_t n_pop[8], uint32_t &tmax,
+                     std::string &err) {
   if (!(cfg.scale > 0.0 && cfg.scale <= 64.0)) {
     err = "scale must lie in (0, 64]";
     return SNN_E_INVAL;
@@ -109,7 +114,6 @@ int sample_instance(const snn_instance_cfg &cfg, uint32_t syn_format, uint32_t w
   out.cfg.conn = nullptr;
   out.conn = connectivity(cfg);
 
-  uint32_t n_pop[8];
   population_sizes(cfg.scale, n_pop);
   out.pop_off[0] = 0;
   for (int p = 0; p < 8; ++p) out.pop_off[p + 1] = out.pop_off[p] + n_pop[p];
@@ -136,7 +140,7 @@ int sample_instance(const snn_instance_cfg &cfg, uint32_t syn_format, uint32_t w
   out.w_ext_q = int32_t(wq_ext);
 
   // Thalamic drive: Poisson with mean v_th K dt (dt = 1e-4 s), or a constant.
-  uint32_t tmax = 0;
+  tmax = 0;
   for (int p = 0; p < 8; ++p) {
     if (cfg.bg_const_T >= 0) {
       if (cfg.bg_const_T > kMaxPoisson) {
@@ -164,7 +168,7 @@ int sample_instance(const snn_instance_cfg &cfg, uint32_t syn_format, uint32_t w
     }
 
   // Population pairs in generation order (target-major).
-  std::vector<Pair> pairs;
+  pairs.clear();
   uint64_t S = 0;
   const double w_f = mc.w_f;
   for (uint32_t b = 0; b < 8; ++b)
@@ -192,6 +196,19 @@ int sample_instance(const snn_instance_cfg &cfg, uint32_t syn_format, uint32_t w
     }
   out.nsyn = S;
 
+  return SNN_OK;
+}
+
+}  // namespace
+
+int sample_instance(const snn_instance_cfg &cfg, uint32_t syn_format, uint32_t win_size,
+                    uint32_t win_origin, bool pad, int threads, HostInstance &out,
+                    std::string &err) {
+  std::vector<Pair> pairs;
+  uint32_t n_pop[8], tmax = 0;
+  int rc = prepare_instance(cfg, syn_format, threads, out, pairs, n_pop, tmax, err);
+  if (rc) return rc;
+  const uint64_t S = out.nsyn;
   const bool comp = syn_format == SNN_SYN_COMPRESSED5;
   if (win_size == 0 || (comp && win_size > (1u << kTargetBlockBits))) {
     err = "target windows must hold 1 .. 65,536 neurons for 16-bit target offsets";
@@ -399,6 +416,238 @@ int sample_instance(const snn_instance_cfg &cfg, uint32_t syn_format, uint32_t w
     err = b;
     return SNN_E_OVERFLOW;
   }
+  return SNN_OK;
+}
+
+
+// Banded layout of the banded LDS engine (band.hip): segments per (sender,
+// target window, delay band) of fixed capacity -- the largest such segment of
+// the sender's population -- so that a segment's address follows from the
+// sender's id.  Built in three passes over a sender-sorted copy of the
+// network (its rows keep generation order, so the result does not depend on
+// the thread count): per-thread row counts, the rows themselves, then per row
+// the segment lengths (capacities) and the placement.
+int sample_instance_banded(const snn_instance_cfg &cfg, uint32_t syn_format, uint32_t win_size,
+                           uint32_t band_h, int threads, HostInstance &out, std::string &err) {
+  std::vector<Pair> pairs;
+  uint32_t n_pop[8], tmax = 0;
+  int rc = prepare_instance(cfg, syn_format, threads, out, pairs, n_pop, tmax, err);
+  if (rc) return rc;
+  const uint64_t S = out.nsyn;
+  const bool comp = syn_format == SNN_SYN_COMPRESSED5;
+  const uint32_t OB = band_offset_bits(band_h);
+  if (!OB || (band_h & (band_h - 1u)) || band_h > 64u) {
+    err = "ring rows of the banded layout must be 8, 16, 32 or 64";
+    return SNN_E_INVAL;
+  }
+  const uint32_t NB = band_count(band_h);
+  if (win_size == 0 || (comp && win_size > (1u << OB))) {
+    err = "target windows too large for the banded compressed records";
+    return SNN_E_RANGE;
+  }
+  const uint32_t n = out.n;
+  const uint32_t nwin = (n + win_size - 1) / win_size;
+  out.win_size = win_size;
+  out.win_origin = 0;
+  out.win_first = 0;
+  out.nwin = nwin;
+  out.band_h = band_h;
+  out.nband = NB;
+  out.padded = true;
+  const uint32_t key0 = uint32_t(cfg.seed), key1 = uint32_t(cfg.seed >> 32);
+
+  const int P = int(std::max<uint64_t>(1, std::min<uint64_t>(uint64_t(threads), S ? S : 1)));
+  std::vector<uint64_t> lo(P + 1);
+  for (int t = 0; t <= P; ++t) lo[t] = S / P * t + std::min<uint64_t>(S % P, t);
+  auto locate = [&](uint64_t e) {
+    size_t i = std::upper_bound(pairs.begin(), pairs.end(), e,
+                                [](uint64_t v, const Pair &p) { return v < p.first; }) -
+               pairs.begin();
+    return i - 1;
+  };
+
+  // Pass 1: synapses per sender and thread.
+  std::vector<std::vector<uint32_t>> cur(P);
+  parallel_for(P, [&](int t) {
+    std::vector<uint32_t> &c = cur[t];
+    c.assign(n, 0);
+    if (lo[t] == lo[t + 1]) return;
+    size_t pi = locate(lo[t]);
+    for (uint64_t e = lo[t]; e < lo[t + 1]; ++e) {
+      while (e >= pairs[pi].first + pairs[pi].count) ++pi;
+      const Pair &pr = pairs[pi];
+      const uint32_t k = uint32_t(e - pr.first);
+      const Philox4 r = philox4x32_10(k, 2u * (pr.tgt * 8u + pr.src), 0, kStreamSynapse, key0, key1);
+      c[pr.src0 + scale_word(r.v[0], pr.nsrc)] += 1;
+    }
+  });
+  std::vector<uint64_t> row(size_t(n) + 1, 0);
+  for (uint32_t pre = 0; pre < n; ++pre) {
+    uint32_t run = 0;
+    for (int t = 0; t < P; ++t) {
+      const uint32_t c = cur[t][pre];
+      cur[t][pre] = run;
+      run += c;
+    }
+    row[pre + 1] = row[pre] + run;
+  }
+
+  // Pass 2: the sender-sorted rows, generation order within a row:
+  // low word the weight (2^-8 pA, or 2^-5 pA compressed), high word
+  // receiver << 6 | delay.
+  std::vector<uint64_t> tmp(S);
+  std::atomic<int> bad{0};
+  std::vector<std::vector<int64_t>> insum(P);
+  parallel_for(P, [&](int t) {
+    std::vector<uint32_t> &c = cur[t];
+    std::vector<int64_t> &in = insum[t];
+    in.assign(n, 0);
+    if (lo[t] == lo[t + 1]) return;
+    size_t pi = locate(lo[t]);
+    for (uint64_t e = lo[t]; e < lo[t + 1]; ++e) {
+      while (e >= pairs[pi].first + pairs[pi].count) ++pi;
+      const Pair &pr = pairs[pi];
+      const uint32_t k = uint32_t(e - pr.first);
+      const uint32_t code = 2u * (pr.tgt * 8u + pr.src);
+      const Philox4 r = philox4x32_10(k, code, 0, kStreamSynapse, key0, key1);
+      const Philox4 s2 = philox4x32_10(k, code + 1u, 0, kStreamSynapse, key0, key1);
+      const uint32_t pre = pr.src0 + scale_word(r.v[0], pr.nsrc);
+      const uint32_t post = pr.tgt0 + scale_word(r.v[1], pr.ntgt);
+      double w = pr.mu_w + pr.sd_w * gauss(r.v[2], r.v[3]);
+      if (pr.mu_w > 0.0 && w < 0.0) w = 0.0;
+      if (pr.mu_w < 0.0 && w > 0.0) w = 0.0;
+      const double dr = std::nearbyint(pr.mu_d + pr.sd_d * gauss(s2.v[0], s2.v[1]));
+      const uint32_t d = dr < 1.0 ? 1u : (dr > double(kMaxDelay) ? uint32_t(kMaxDelay) : uint32_t(dr));
+      int32_t wv, wq;
+      if (comp) {
+        const double q = std::nearbyint(w * 32.0);
+        if (!(q >= -32768.0 && q <= 32767.0)) {
+          bad.store(2);
+          continue;
+        }
+        wv = int32_t(q);
+        wq = wv * 8;
+      } else {
+        const double q = std::nearbyint(w * 256.0);
+        if (!(std::fabs(q) < 2147483647.0)) {
+          bad.store(1);
+          continue;
+        }
+        wv = wq = int32_t(q);
+      }
+      tmp[row[pre] + c[pre]++] = uint64_t(uint32_t(wv)) | (uint64_t((post << 6) | d) << 32);
+      in[post] += std::llabs(int64_t(wq));
+    }
+  });
+  cur.clear();
+  cur.shrink_to_fit();
+  if (bad.load() == 2) {
+    err = "a weight does not fit the 16-bit compressed encoding";
+    return SNN_E_RANGE;
+  }
+  if (bad.load() == 1) {
+    err = "a weight does not fit int32 fixed point";
+    return SNN_E_RANGE;
+  }
+  int64_t worst = 0;
+  for (uint32_t i = 0; i < n; ++i) {
+    int64_t s = 0;
+    for (int t = 0; t < P; ++t) s += insum[t][i];
+    worst = std::max(worst, s);
+  }
+  insum.clear();
+  worst += int64_t(tmax) * std::llabs(int64_t(out.w_ext_q));
+  if (worst >= 2147483647LL) {
+    char b[128];
+    std::snprintf(b, sizeof b, "worst-case input %lld exceeds the int32 accumulator", (long long)worst);
+    err = b;
+    return SNN_E_OVERFLOW;
+  }
+  out.outdeg.assign(n, 0);
+  for (uint32_t pre = 0; pre < n; ++pre) out.outdeg[pre] = uint32_t(row[pre + 1] - row[pre]);
+
+  // Senders in P contiguous ranges of about equal synapse counts.
+  std::vector<uint32_t> sr(P + 1, n);
+  sr[0] = 0;
+  for (int t = 1; t < P; ++t)
+    sr[t] = uint32_t(std::lower_bound(row.begin(), row.end(), S / P * uint64_t(t)) - row.begin());
+  for (int t = 1; t <= P; ++t) sr[t] = std::max(sr[t], sr[t - 1]);
+  auto cls_of = [&](uint32_t pre) {
+    uint32_t c = 0;
+    while (pre >= out.pop_off[c + 1]) ++c;
+    return c;
+  };
+  const size_t nkey = size_t(nwin) * NB;   // (window, band) of one sender
+  auto key_of = [&](uint64_t rec) {
+    const uint32_t hiw = uint32_t(rec >> 32);
+    return size_t((hiw >> 6) / win_size) * NB + band_of(hiw & 63u, band_h);
+  };
+
+  // Pass 3: capacities, the largest segment per (window, band, class).
+  std::vector<std::vector<uint32_t>> capt(P);
+  parallel_for(P, [&](int t) {
+    std::vector<uint32_t> &cp = capt[t];
+    cp.assign(nkey * 8, 0);
+    std::vector<uint32_t> cnt(nkey, 0);
+    for (uint32_t pre = sr[t]; pre < sr[t + 1]; ++pre) {
+      const uint32_t c = cls_of(pre);
+      for (uint64_t e = row[pre]; e < row[pre + 1]; ++e) ++cnt[key_of(tmp[e])];
+      for (uint64_t e = row[pre]; e < row[pre + 1]; ++e) {
+        const size_t kk = key_of(tmp[e]);
+        uint32_t &m = cp[kk * 8 + c];
+        m = std::max(m, cnt[kk]);
+        cnt[kk] = 0;
+      }
+    }
+  });
+  out.cls_cap.assign(nkey * 8, 0);
+  for (int t = 0; t < P; ++t)
+    for (size_t i = 0; i < nkey * 8; ++i) out.cls_cap[i] = std::max(out.cls_cap[i], capt[t][i]);
+  capt.clear();
+  out.cls_base.assign(nkey * 8, 0);
+  uint64_t run = 0;
+  for (size_t kk = 0; kk < nkey; ++kk)
+    for (int c = 0; c < 8; ++c) {
+      out.cls_base[kk * 8 + c] = run;
+      run += uint64_t(n_pop[c]) * out.cls_cap[kk * 8 + c];
+    }
+  out.nrec = run;
+  out.rec8.clear();
+  out.rec4.clear();
+  out.tgt16.clear();
+  out.w16.clear();
+  out.d8.clear();
+  if (comp)
+    out.rec4.assign(run, 0);
+  else
+    out.rec8.assign(run, 0);
+
+  // Pass 4: placement, generation order within a segment.  Unused slots stay
+  // zero (weight 0: they add nothing).
+  parallel_for(P, [&](int t) {
+    std::vector<uint64_t> at(nkey, 0);
+    std::vector<uint32_t> stamp(nkey, ~0u);
+    for (uint32_t pre = sr[t]; pre < sr[t + 1]; ++pre) {
+      const uint32_t c = cls_of(pre);
+      for (uint64_t e = row[pre]; e < row[pre + 1]; ++e) {
+        const uint64_t r = tmp[e];
+        const size_t kk = key_of(r);
+        if (stamp[kk] != pre) {
+          stamp[kk] = pre;
+          at[kk] = out.cls_base[kk * 8 + c] + uint64_t(pre - out.pop_off[c]) * out.cls_cap[kk * 8 + c];
+        }
+        const uint64_t pos = at[kk]++;
+        if (comp) {
+          const uint32_t hiw = uint32_t(r >> 32), d = hiw & 63u, post = hiw >> 6;
+          const uint32_t b = uint32_t(kk % NB);
+          out.rec4[pos] = (uint32_t(uint16_t(int16_t(int32_t(uint32_t(r))))) << 16) |
+                          ((d - band_lo(b, band_h)) << OB) | (post % win_size);
+        } else {
+          out.rec8[pos] = r;
+        }
+      }
+    }
+  });
   return SNN_OK;
 }
 

@@ -94,6 +94,9 @@ struct DeviceNet {
   const uint32_t *outdeg = nullptr; // LDS engine: synapses per sender [ntot]
   uint64_t *lflags = nullptr;       // LDS engine: [kSlots][windows] flag words
   uint32_t *llist = nullptr;        // LDS engine: [kSlots][ntot] senders beyond the inline ones
+  uint32_t band_h = 0;              // banded engine: ring rows in LDS (64, 16 or 8), else 0
+  uint32_t *ghist = nullptr;        // banded engine: [64][ntot] sender ids of each step beyond
+                                    // the block's LDS history (same values from every block)
 };
 
 struct LaunchShape {
@@ -122,5 +125,19 @@ hipError_t launch_lds(const DeviceNet &d, uint32_t group, uint32_t n_groups, uin
                       uint32_t nwin, uint32_t n, hipStream_t s);
 // Co-resident blocks of the LDS kernel with window capacity wn (320 or 512).
 int lds_max_grid(uint32_t wn);
+
+// Banded LDS engine (band.hip): kernel variants, each a block size, a window
+// capacity (neurons), the ring rows kept in LDS and the sender ids per step
+// its LDS history holds.  Variants are ordered by window capacity.
+struct BandVariant {
+  uint32_t block, wn, h, hc;
+};
+constexpr uint32_t kNumBandVariants = 4;
+extern const BandVariant kBandVariants[kNumBandVariants];
+// One cooperative launch of every window (d.n_lwin blocks) runs n steps from
+// ctl->t_base and advances it.
+hipError_t launch_band(const DeviceNet &d, uint32_t variant, uint32_t n, hipStream_t s);
+// Co-resident blocks of a variant (at most one per CU, at most kLdsMaxGrid).
+int band_max_grid(uint32_t variant);
 
 }  // namespace snn

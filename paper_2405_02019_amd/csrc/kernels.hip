@@ -13,7 +13,7 @@
 // dependent chain: thalamic tables sit in LDS and are scanned eight entries at
 // a time, and each thread issues the record loads of all its synapses before
 // any of their atomics.
-#include "engine.hpp"
+#include "device.hpp"
 
 namespace snn {
 
@@ -44,10 +44,6 @@ hipError_t launch_propagators(const DeviceNet &d, hipStream_t s) {
 // ---------------------------------------------------------------------------
 // Shared pieces of the neuron update.
 // ---------------------------------------------------------------------------
-struct Props {
-  float p11, p22, p21;
-};
-
 // Thalamic tables in LDS (or straight from global memory when the batch's
 // tables are too large); copied by the whole block.
 struct ThrTables {
@@ -77,25 +73,6 @@ __device__ __forceinline__ uint32_t thalamic_count(const uint32_t *tab, uint2 m,
     while (T < m.y && u >= tab[m.x + T]) ++T;
   }
   return T;
-}
-
-__device__ __forceinline__ uint32_t population(const InstDev *__restrict__ ip, uint32_t local) {
-  uint32_t p = 0;
-#pragma unroll
-  for (int k = 1; k < 8; ++k) p += local >= ip->pop_off[k] ? 1u : 0u;
-  return p;
-}
-
-// Population code of a quad: 3 bits per neuron, and bit 12 + m set when
-// neuron m is a real neuron of the instance (not padding).
-__device__ __forceinline__ uint32_t quad_code(const InstDev *__restrict__ ip, uint32_t lq) {
-  uint32_t c = 0;
-#pragma unroll
-  for (int m = 0; m < 4; ++m) {
-    const uint32_t local = lq * 4u + uint32_t(m);
-    if (local < ip->n) c |= (population(ip, local) << (3 * m)) | (1u << (12 + m));
-  }
-  return c;
 }
 
 // eqn:mem and eqn:ref for step t: the membrane update of the quad's real
@@ -128,28 +105,6 @@ __device__ __forceinline__ uint32_t lif_quad(uint32_t code, Props k, float (&u)[
   return flags;
 }
 
-// lif_quad for quads whose padding neurons hold u = i = 0 and r = 0: such a
-// neuron stays at 0 below the threshold, so every lane updates all four
-// neurons without tests or branches.  Same arithmetic as lif_quad.
-__device__ __forceinline__ uint32_t lif_quad_padded(Props k, float (&u)[4], const float (&i)[4],
-                                                    uint32_t &r4) {
-  uint32_t flags = 0, rout = 0;
-#pragma unroll
-  for (int m = 0; m < 4; ++m) {
-    const uint32_t r = (r4 >> (8 * m)) & 0xFFu;
-    const float a = k.p22 * u[m];
-    const float b = k.p21 * i[m];
-    const float xm = a + b;
-    const bool spike = r == 0 && xm >= kTheta;
-    u[m] = (r == 0 && !spike) ? xm : 0.0f;
-    const uint32_t rn = spike ? kRefSteps : (r ? r - 1u : 0u);
-    flags |= uint32_t(spike) << m;
-    rout |= rn << (8 * m);
-  }
-  r4 = rout;
-  return flags;
-}
-
 // Step t of a quad: the thalamic counts T_t (packed one byte per neuron into
 // tp, their sum added to tsum) and the membrane update.  tab/meta hold the
 // thalamic tables; meta[mbase + population] = (offset, length).
@@ -173,36 +128,6 @@ __device__ __forceinline__ uint32_t decide_quad(const uint32_t *tab, const uint2
   tp = tpk;
   return lif_quad(code, k, u, i, r4);
 }
-
-// eqn:psc: I <- p11 I + (T w_ext + W) 2^-8, the input summed as an integer.
-__device__ __forceinline__ float next_current(float i, int32_t T, int32_t wext, int32_t w,
-                                              float p11) {
-  const int32_t q = T * wext + w;
-  const float c = p11 * i;
-  const float e = __int2float_rn(q) * 0x1p-8f;
-  return c + e;
-}
-
-__device__ __forceinline__ uint64_t lanemask_lt() {
-  const uint32_t lane = __lane_id();
-  return lane == 0 ? 0ull : (~0ull >> (64 - lane));
-}
-
-// Wave-level compaction of up to 4 spikes per lane: this lane's offset in the
-// wave's output and the wave's total.
-__device__ __forceinline__ void wave_compact(uint32_t flags, uint32_t &lane_off, uint32_t &total) {
-  const uint64_t lt = lanemask_lt();
-  lane_off = 0;
-  total = 0;
-#pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    const uint64_t b = __ballot((flags >> j) & 1u);
-    lane_off += __popcll(b & lt);
-    total += __popcll(b);
-  }
-}
-
-__device__ __forceinline__ float4 ld4(const float *p) { return *reinterpret_cast<const float4 *>(p); }
 
 template <int BS>
 __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t *s_tmp,
@@ -525,18 +450,6 @@ hipError_t launch_stepwise(const DeviceNet &d, const LaunchShape &sh, uint32_t n
 // ---------------------------------------------------------------------------
 constexpr uint32_t kSpec = 64;   // list entries fetched together with the count
 
-__device__ __forceinline__ uint32_t ld_ag(const uint32_t *p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ uint64_t ld_ag(const uint64_t *p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ void st_ag(uint32_t *p, uint32_t v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ void st_ag(uint64_t *p, uint64_t v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
 __device__ __forceinline__ SegStage ld_entry(const SegEntry *e) {
   SegStage r;
   r.start = ld_ag(&e->start);
@@ -944,20 +857,6 @@ __device__ __forceinline__ uint32_t sender_gid(const uint32_t *llist, uint32_t n
   return w0 + ld_ag(llist + size_t(lslot) * ntot + w0 + kk);
 }
 
-// Exclusive prefix sum of v over the wave's lanes, and the wave's total: one
-// ballot per bit of v, so the cost grows with the bit length of the largest
-// value, not with the lane count (all lanes active).
-__device__ __forceinline__ uint32_t wave_prefix(uint32_t v, uint32_t &total) {
-  uint32_t p = 0, tot = 0;
-  for (uint32_t b = 0; b < 32u && __ballot(int(v >> b)) != 0ull; ++b) {
-    const uint64_t m = __ballot(int((v >> b) & 1u));
-    p += __builtin_amdgcn_mbcnt_hi(uint32_t(m >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(m), 0u)) << b;
-    tot += uint32_t(__popcll(m)) << b;
-  }
-  total = tot;
-  return p;
-}
-
 // UR record slots per lane.  The wave's senders of a batch are held one per
 // lane (segment address and capacity); their segments are cut into 64-record
 // pieces, numbered sender by sender.  load() takes the next UR pieces, one per
@@ -1108,7 +1007,7 @@ __global__ __launch_bounds__(256) void k_lds(DeviceNet d, uint32_t n_steps, uint
   }
 
   float U[4] = {0, 0, 0, 0}, I[4] = {0, 0, 0, 0};
-  uint32_t R = 0, PC = 0, c_spk = 0, c_poi = 0;
+  uint32_t R = 0, c_spk = 0, c_poi = 0;
   uint32_t OD[4] = {0, 0, 0, 0};
   int64_t c_con = 0;
   uint64_t c_ev = 0;
@@ -1119,7 +1018,6 @@ __global__ __launch_bounds__(256) void k_lds(DeviceNet d, uint32_t n_steps, uint
     U[0] = uv.x; U[1] = uv.y; U[2] = uv.z; U[3] = uv.w;
     I[0] = iv.x; I[1] = iv.y; I[2] = iv.z; I[3] = iv.w;
     R = d.R4[q];
-    PC = quad_code(ip, q - ip->gbase / 4);
     const uint4 od = *reinterpret_cast<const uint4 *>(d.outdeg + 4 * size_t(q));
     OD[0] = od.x; OD[1] = od.y; OD[2] = od.z; OD[3] = od.w;
   }

@@ -45,11 +45,16 @@ struct snn_net {
   uint64_t *staging = nullptr;      // pinned host buffer for raster drains
   size_t staging_cap = 0;           // its capacity in entries
   size_t raster_sorted = 0;         // later drains hold later steps: only the tail needs sorting
+  uint64_t raster_version = 0;      // bumped whenever the stored raster changes
+  std::vector<uint64_t> by_inst;    // several instances: the sorted raster grouped by instance
+  std::vector<size_t> by_inst_off;  // [n_instances + 1] into by_inst
+  uint64_t by_inst_version = ~0ull; // raster version by_inst was built from
   uint64_t t = 0;
   uint64_t pending = 0;             // worst-case raster entries since the last drain
   bool overflowed = false;
   bool dead = false;
   std::vector<uint2> lds_groups;    // LDS engine: launches (first window, windows)
+  uint32_t band_variant = 0;        // banded engine: kernel variant (kBandVariants)
   std::string err;
   double build_seconds = 0.0;
 };
@@ -142,6 +147,7 @@ int drain(snn_net *h) {
     }
     HIP_OK(h, hipMemcpy(h->staging, h->d.raster, m * sizeof(uint64_t), hipMemcpyDeviceToHost));
     h->raster.insert(h->raster.end(), h->staging, h->staging + m);
+    ++h->raster_version;
   }
   if (c.raster_n || c.overflow) HIP_OK(h, launch_reset_raster(h->d, h->stream));
   h->pending = 0;
@@ -235,9 +241,11 @@ bool sort_raster_tail_windows(std::vector<uint64_t> &r, size_t from,
 // Orders the raster entries drained since the last call.
 void sort_drained(snn_net *h) {
   if (h->raster_sorted >= h->raster.size()) return;
-  if (h->engine != SNN_ENGINE_LDS || !sort_raster_tail_windows(h->raster, h->raster_sorted, h->im))
+  const bool windows = h->engine == SNN_ENGINE_LDS || h->engine == SNN_ENGINE_BAND;
+  if (!windows || !sort_raster_tail_windows(h->raster, h->raster_sorted, h->im))
     sort_raster_tail(h->raster, h->raster_sorted);
   h->raster_sorted = h->raster.size();
+  ++h->raster_version;
 }
 
 uint64_t spike_bound(const snn_net *h, uint64_t steps) {
@@ -325,6 +333,40 @@ int plan_lds(const std::vector<InstMeta> &im, uint32_t block, uint32_t grid, Lds
   return SNN_E_RANGE;
 }
 
+// Banded engine plan: the first kernel variant (by window capacity) and the
+// shortest window (at least 256 neurons) that put every instance into one
+// co-resident launch; a requested grid size fixes the number of windows.
+int plan_band(const std::vector<InstMeta> &im, uint32_t block, uint32_t grid, LdsPlan &p,
+              uint32_t &variant, std::string &why) {
+  uint64_t nq = 0;
+  for (const InstMeta &m : im) nq += quads_of(m);
+  for (uint32_t v = 0; v < kNumBandVariants; ++v) {
+    const BandVariant &bv = kBandVariants[v];
+    if (block && block != bv.block) continue;
+    const int g = band_max_grid(v);
+    if (g <= 0) continue;
+    const uint32_t maxg = uint32_t(g);
+    if (grid) {
+      for (uint32_t L = bv.wn; L >= 4; L -= 4)
+        if (make_plan(im, L, bv.wn, maxg, p) && p.groups.size() == 1 && p.total == grid) {
+          variant = v;
+          return SNN_OK;
+        }
+      continue;
+    }
+    for (uint32_t L = 256; L <= bv.wn; L += 4) {
+      if (4 * nq > uint64_t(maxg) * L) continue;
+      if (make_plan(im, L, bv.wn, maxg, p) && p.groups.size() == 1) {
+        variant = v;
+        return SNN_OK;
+      }
+    }
+  }
+  why = grid ? "no banded kernel gives the requested number of blocks in one launch"
+             : "the network needs more windows than one co-resident launch of the banded engine holds";
+  return SNN_E_RANGE;
+}
+
 // Persistent grid: 4 neurons per quad, `qpt` quads per thread, at most the
 // co-resident block count of the kernel.  Fewer blocks make the per-step grid
 // barrier cheaper; more threads give the transfer phase more parallelism.
@@ -361,6 +403,10 @@ hipError_t launch_lds_chunk(snn_net *h, uint32_t n) {
 }
 
 int queue_steps(snn_net *h, uint32_t n) {
+  if (h->engine == SNN_ENGINE_BAND) {
+    HIP_OK(h, launch_band(h->d, h->band_variant, n, h->stream));
+    return SNN_OK;
+  }
   if (h->engine == SNN_ENGINE_LDS) {
     HIP_OK(h, launch_lds_chunk(h, n));
     return SNN_OK;
@@ -429,7 +475,7 @@ int snn_build(const snn_config *cfg, snn_net **out) {
     return fail(nullptr, SNN_E_INVAL, "need 1..%u instances", kMaxInstances);
   if (cfg->syn_format > SNN_SYN_COMPRESSED5)
     return fail(nullptr, SNN_E_INVAL, "unknown synapse format %u", cfg->syn_format);
-  if (cfg->engine > SNN_ENGINE_LDS)
+  if (cfg->engine > SNN_ENGINE_BAND)
     return fail(nullptr, SNN_E_INVAL, "unknown engine %u", cfg->engine);
   const auto t_start = std::chrono::steady_clock::now();
 
@@ -466,21 +512,26 @@ int snn_build(const snn_config *cfg, snn_net **out) {
 
   // ---- engine: the LDS-resident ring needs its whole network in the
   // aggregate LDS (one 512- or 256-neuron window per co-resident block) ----
+  // AUTO: the LDS engine when the network's 64-row ring fits the chip's LDS,
+  // else the banded engine (fewer ring rows in LDS), else the persistent one.
   h->engine = cfg->engine == SNN_ENGINE_AUTO ? SNN_ENGINE_LDS : cfg->engine;
-  uint32_t lds_window = 0;
+  uint32_t lds_window = 0;   // LDS or banded engine: kernel window capacity
   LdsPlan plan;
-  if (h->engine == SNN_ENGINE_LDS) {
-    uint32_t tab = 0;
-    for (uint32_t k = 0; k < ni; ++k) tab = std::max(tab, thalamic_table_max(cfg->inst[k]));
+  uint32_t tab = 0;
+  for (uint32_t k = 0; k < ni; ++k) tab = std::max(tab, thalamic_table_max(cfg->inst[k]));
+  for (int attempt = 0; attempt < 2; ++attempt) {
+    if (h->engine != SNN_ENGINE_LDS && h->engine != SNN_ENGINE_BAND) break;
     std::string why;
     int prc = SNN_E_RANGE;
     if (tab > kLdsTab) {
       char b[128];
-      std::snprintf(b, sizeof b, "the LDS engine holds thalamic tables of at most %u entries (need %u)",
+      std::snprintf(b, sizeof b, "the LDS engines hold thalamic tables of at most %u entries (need %u)",
                     kLdsTab, tab);
       why = b;
-    } else {
+    } else if (h->engine == SNN_ENGINE_LDS) {
       prc = plan_lds(h->im, cfg->block_size, cfg->grid_blocks, plan, why);
+    } else {
+      prc = plan_band(h->im, cfg->block_size, cfg->grid_blocks, plan, h->band_variant, why);
     }
     if (prc == SNN_OK) {
       lds_window = plan.wn;
@@ -492,14 +543,20 @@ int snn_build(const snn_config *cfg, snn_net **out) {
         w0 += plan.nwin[k];
       }
       h->lds_groups = plan.groups;
-    } else {
-      if (cfg->engine == SNN_ENGINE_LDS) {
-        fail(h, prc, "%s", why.c_str());
-        return bail(prc);
-      }
-      h->engine = SNN_ENGINE_PERSISTENT;
+      break;
     }
+    if (cfg->engine != SNN_ENGINE_AUTO) {
+      fail(h, prc, "%s", why.c_str());
+      return bail(prc);
+    }
+    h->engine = h->engine == SNN_ENGINE_LDS ? SNN_ENGINE_BAND : SNN_ENGINE_PERSISTENT;
+    if (h->engine == SNN_ENGINE_PERSISTENT) break;
   }
+  if (!lds_window && (h->engine == SNN_ENGINE_LDS || h->engine == SNN_ENGINE_BAND))
+    h->engine = SNN_ENGINE_PERSISTENT;
+  const bool banded = h->engine == SNN_ENGINE_BAND;
+  const uint32_t band_h = banded ? kBandVariants[h->band_variant].h : 0u;
+  const uint32_t nband = banded ? band_count(band_h) : 1u;
 
   // ---- sample every instance on the host ----
   std::vector<HostInstance> hi(ni);
@@ -514,8 +571,10 @@ int snn_build(const snn_config *cfg, snn_net **out) {
       wsize = 1u << kTargetBlockBits;
     }
     std::string e;
-    int rc = sample_instance(cfg->inst[k], cfg->syn_format, wsize, worigin, lds_window != 0,
-                             cfg->host_threads, hi[k], e);
+    int rc = banded ? sample_instance_banded(cfg->inst[k], cfg->syn_format, wsize, band_h,
+                                             cfg->host_threads, hi[k], e)
+                    : sample_instance(cfg->inst[k], cfg->syn_format, wsize, worigin, lds_window != 0,
+                                      cfg->host_threads, hi[k], e);
     if (rc) {
       fail(h, rc, "instance %u: %s", k, e.c_str());
       return bail(rc);
@@ -539,6 +598,7 @@ int snn_build(const snn_config *cfg, snn_net **out) {
   d.ntot = ntot;
   d.nquads = ntot / 4;
   d.lds_window = lds_window;
+  d.band_h = band_h;
   d.n_lwin = plan.total;
   d.nwin_max = nwin_max;
   d.syn_format = cfg->syn_format;
@@ -609,8 +669,9 @@ int snn_build(const snn_config *cfg, snn_net **out) {
   uint2 *d_wrel = nullptr;
   uint4 *d_lwin = nullptr;
   uint32_t *d_outdeg = nullptr;
+  if (banded) ALLOC(d.ghist, size_t(64) * d.ntot);
   if (lds_window) {
-    ALLOC(d_wcls, size_t(nwin_lds) * kWinClasses);
+    ALLOC(d_wcls, size_t(nwin_lds) * nband * kWinClasses);
     ALLOC(d_wrel, nwin_lds);
     ALLOC(d_lwin, nwin_lds);
     ALLOC(d_outdeg, d.ntot);
@@ -682,7 +743,7 @@ int snn_build(const snn_config *cfg, snn_net **out) {
   if (lds_window) {
     // Per window: its neurons, the sender classes of its instance, and the
     // windows of that instance (the only ones whose senders reach it).
-    std::vector<WinClass> wcls(size_t(nwin_lds) * kWinClasses);
+    std::vector<WinClass> wcls(size_t(nwin_lds) * nband * kWinClasses);
     std::vector<uint2> wrel(nwin_lds);
     std::vector<uint4> lwin(nwin_lds);
     std::vector<uint32_t> outdeg(d.ntot, 0);
@@ -696,13 +757,16 @@ int snn_build(const snn_config *cfg, snn_net **out) {
         const uint32_t first = w * m.wlen;
         lwin[gw] = make_uint4(m.gbase + first, std::min(m.wlen, span - first), k, 0);
         wrel[gw] = make_uint2(m.win0, m.win0 + m.nwin);
-        for (int c = 0; c < 8; ++c) {
-          WinClass &e = wcls[size_t(gw) * kWinClasses + c];
-          e.base = rb + x.cls_base[size_t(w) * 8 + c];
-          e.first = m.gbase + x.pop_off[c];
-          e.n = x.pop_off[c + 1] - x.pop_off[c];
-          e.cap = x.cls_cap[size_t(w) * 8 + c];
-        }
+        // [window][band][class]; the LDS engine has one band.
+        for (uint32_t b = 0; b < nband; ++b)
+          for (int c = 0; c < 8; ++c) {
+            const size_t src = (size_t(w) * nband + b) * 8 + c;
+            WinClass &e = wcls[(size_t(gw) * nband + b) * kWinClasses + c];
+            e.base = rb + x.cls_base[src];
+            e.first = m.gbase + x.pop_off[c];
+            e.n = x.pop_off[c + 1] - x.pop_off[c];
+            e.cap = x.cls_cap[src];
+          }
       }
       std::copy(x.outdeg.begin(), x.outdeg.end(), outdeg.begin() + m.gbase);
       rb += x.nrec;
@@ -757,7 +821,8 @@ int snn_build(const snn_config *cfg, snn_net **out) {
       hipMemset(d.ctl, 0, sizeof(Control)) != hipSuccess ||
       (d.lflags && hipMemset(d.lflags, 0, kSlots * size_t(nwin_lds) * sizeof(uint64_t)) != hipSuccess) ||
       (d.blk_ctr && hipMemset(d.blk_ctr, 0, 4 * size_t(nwin_lds) * sizeof(int64_t)) != hipSuccess) ||
-      (d.lgroup && hipMemset(d.lgroup, 0, plan.groups.size() * sizeof(uint2)) != hipSuccess)) {
+      (d.lgroup && hipMemset(d.lgroup, 0, plan.groups.size() * sizeof(uint2)) != hipSuccess) ||
+      (d.ghist && hipMemset(d.ghist, 0, size_t(64) * d.ntot * sizeof(uint32_t)) != hipSuccess)) {
     fail(h, SNN_E_HIP, "device memset failed");
     return bail(SNN_E_HIP);
   }
@@ -770,8 +835,8 @@ int snn_build(const snn_config *cfg, snn_net **out) {
   // ---- engine ----
   h->shape.block = 256;
   h->shape.scatter_blocks = 1024;
-  if (h->engine == SNN_ENGINE_LDS) {
-    h->shape.block = 256;
+  if (h->engine == SNN_ENGINE_LDS || h->engine == SNN_ENGINE_BAND) {
+    h->shape.block = banded ? kBandVariants[h->band_variant].block : 256;
     h->shape.grid = plan.total;
     h->shape.qpt = 1;
   } else if (h->engine == SNN_ENGINE_PERSISTENT) {
@@ -840,30 +905,62 @@ int snn_read_spikes(snn_net *h, uint32_t inst, uint64_t t0, uint64_t t1, uint32_
   t0 = std::min<uint64_t>(t0, 0xFFFFFFFFull);
   t1 = std::min<uint64_t>(t1, 0x100000000ull);
   sort_drained(h);
-  auto lo = std::lower_bound(h->raster.begin(), h->raster.end(), t0 << 32);
-  auto hi = t1 >= 0x100000000ull ? h->raster.end()
-                                 : std::lower_bound(h->raster.begin(), h->raster.end(), t1 << 32);
-  uint64_t cnt = 0;
-  if (h->im.size() == 1) {   // every entry is the one instance's
-    cnt = uint64_t(hi - lo);
-  } else {
-    for (auto it = lo; it < hi; ++it) {
-      const uint32_t g = uint32_t(*it);
-      cnt += (g >= m.gbase && g < m.gbase + m.n);
+  // The entries of one instance, sorted by (step, id): the whole raster for
+  // one instance, else its part of the raster grouped by instance (built
+  // once per raster version by a stable counting sort on the instance).
+  const uint64_t *first = h->raster.data(), *last = h->raster.data() + h->raster.size();
+  if (h->im.size() > 1) {
+    if (h->by_inst_version != h->raster_version) {
+      const size_t ni = h->im.size();
+      std::vector<uint32_t> which(h->raster.size());
+      h->by_inst_off.assign(ni + 1, 0);
+      for (size_t i = 0; i < h->raster.size(); ++i) {
+        const uint32_t g = uint32_t(h->raster[i]);
+        size_t a = 0, b = ni;   // last instance with gbase <= g
+        while (b - a > 1) {
+          const size_t c = (a + b) / 2;
+          if (h->im[c].gbase <= g) a = c; else b = c;
+        }
+        which[i] = uint32_t(a);
+        ++h->by_inst_off[a + 1];
+      }
+      for (size_t k = 0; k < ni; ++k) h->by_inst_off[k + 1] += h->by_inst_off[k];
+      std::vector<size_t> at(h->by_inst_off.begin(), h->by_inst_off.end() - 1);
+      h->by_inst.resize(h->raster.size());
+      for (size_t i = 0; i < h->raster.size(); ++i) h->by_inst[at[which[i]]++] = h->raster[i];
+      h->by_inst_version = h->raster_version;
     }
+    first = h->by_inst.data() + h->by_inst_off[inst];
+    last = h->by_inst.data() + h->by_inst_off[inst + 1];
   }
+  const uint64_t *lo = std::lower_bound(first, last, t0 << 32);
+  const uint64_t *hi = t1 >= 0x100000000ull ? last : std::lower_bound(first, last, t1 << 32);
+  const uint64_t cnt = uint64_t(hi - lo);
   *n_out = cnt;
   if (!steps && !ids) return SNN_OK;
   if (cnt > cap) return fail(h, SNN_E_RANGE, "%llu spikes, buffer holds %llu",
                              (unsigned long long)cnt, (unsigned long long)cap);
   uint64_t k = 0;
-  for (auto it = lo; it < hi; ++it) {
-    const uint32_t g = uint32_t(*it);
-    if (g < m.gbase || g >= m.gbase + m.n) continue;
+  for (const uint64_t *it = lo; it < hi; ++it, ++k) {
     if (steps) steps[k] = uint32_t(*it >> 32);
-    if (ids) ids[k] = g - m.gbase;
-    ++k;
+    if (ids) ids[k] = uint32_t(*it) - m.gbase;
   }
+  return SNN_OK;
+}
+
+int snn_discard_spikes(snn_net *h, uint64_t t_before) {
+  if (!h) return fail(nullptr, SNN_E_INVAL, "handle is NULL");
+  int rc = drain(h);
+  if (rc) return rc;
+  sort_drained(h);
+  const uint64_t key = std::min<uint64_t>(t_before, 0x100000000ull);
+  auto end = key >= 0x100000000ull ? h->raster.end()
+                                   : std::lower_bound(h->raster.begin(), h->raster.end(), key << 32);
+  const size_t n = size_t(end - h->raster.begin());
+  h->raster.erase(h->raster.begin(), end);
+  h->raster_sorted -= std::min(h->raster_sorted, n);
+  ++h->raster_version;
+  if (h->raster.capacity() > 4 * h->raster.size() + (size_t(1) << 20)) h->raster.shrink_to_fit();
   return SNN_OK;
 }
 
@@ -941,7 +1038,8 @@ int snn_get_info(const snn_net *h, snn_info *out) {
   out->device_bytes = h->device_bytes;
   out->build_seconds = h->build_seconds;
   out->graphs = h->graph_exec ? 1u : 0u;
-  if (h->engine == SNN_ENGINE_LDS) {
+  out->ring_rows = h->engine == SNN_ENGINE_BAND ? h->d.band_h : uint32_t(kRing);
+  if (h->engine == SNN_ENGINE_LDS || h->engine == SNN_ENGINE_BAND) {
     out->launches_per_chunk = uint32_t(h->lds_groups.size());
     for (const auto &m : h->im) out->window_neurons = std::max(out->window_neurons, m.wlen);
   } else {
@@ -1032,22 +1130,24 @@ int snn_autotune(snn_net *h, uint32_t trial_steps, snn_tune_report *out) {
 
 int snn_time_steps(snn_net *h, uint64_t n_steps, double *elapsed_ms) {
   if (!h || !elapsed_ms) return fail(h, SNN_E_INVAL, "NULL argument");
-  hipEvent_t a, b;
+  hipEvent_t a = nullptr, b = nullptr;
+  // Both events are released on every path, the error paths included.
+  struct Events {
+    hipEvent_t *a, *b;
+    ~Events() {
+      if (*a) (void)hipEventDestroy(*a);
+      if (*b) (void)hipEventDestroy(*b);
+    }
+  } guard{&a, &b};
   HIP_OK(h, hipEventCreate(&a));
   HIP_OK(h, hipEventCreate(&b));
   HIP_OK(h, hipEventRecord(a, h->stream));
-  int rc = snn_step_n(h, n_steps);
-  if (rc) {
-    (void)hipEventDestroy(a);
-    (void)hipEventDestroy(b);
-    return rc;
-  }
+  const int rc = snn_step_n(h, n_steps);
+  if (rc) return rc;
   HIP_OK(h, hipEventRecord(b, h->stream));
   HIP_OK(h, hipEventSynchronize(b));
   float ms = 0.0f;
   HIP_OK(h, hipEventElapsedTime(&ms, a, b));
-  (void)hipEventDestroy(a);
-  (void)hipEventDestroy(b);
   *elapsed_ms = ms;
   return SNN_OK;
 }
@@ -1057,18 +1157,13 @@ int snn_sample_network(const snn_instance_cfg *inst, uint32_t syn_format, int32_
   return snn_sample_network_windows(inst, syn_format, 0, host_threads, out);
 }
 
-int snn_sample_network_windows(const snn_instance_cfg *inst, uint32_t syn_format, uint32_t window,
-                               int32_t host_threads, snn_host_network **out) {
-  if (!inst || !out) return fail(nullptr, SNN_E_INVAL, "NULL argument");
-  *out = nullptr;
-  if (window != 0 && window != 256 && window != 512)
-    return fail(nullptr, SNN_E_INVAL, "window must be 0, 256 or 512");
-  HostInstance x;
-  std::string e;
-  uint32_t wsize = syn_format == SNN_SYN_COMPRESSED5 ? (1u << kTargetBlockBits) : kNoWindows;
-  if (window) wsize = window;
-  int rc = sample_instance(*inst, syn_format, wsize, 0, window != 0, host_threads, x, e);
-  if (rc) return fail(nullptr, rc, "%s", e.c_str());
+}  // extern "C"
+
+namespace {
+
+// Rows of a sampled instance read back from its storage layout, in storage
+// order (by target window, then band, then segment order).
+int read_back(const HostInstance &x, uint32_t syn_format, snn_host_network **out) {
   snn_host_network *n = static_cast<snn_host_network *>(std::calloc(1, sizeof(snn_host_network)));
   if (!n) return fail(nullptr, SNN_E_NOMEM, "host allocation failed");
   n->n_neurons = x.n;
@@ -1085,61 +1180,109 @@ int snn_sample_network_windows(const snn_instance_cfg *inst, uint32_t syn_format
   }
   std::memcpy(n->u0, x.u0.data(), x.n * sizeof(float));
   const bool comp = syn_format == SNN_SYN_COMPRESSED5;
-  // Decode rows in storage order: by target window, then segment order.
+  const uint32_t nb = x.nband;
+  const uint32_t ob = x.band_h ? band_offset_bits(x.band_h) : 0u;
   uint64_t o = 0;
   for (uint32_t i = 0; i < x.n; ++i) {
     n->row_ptr[i] = o;
     uint32_t c = 0;
     while (x.padded && i >= x.pop_off[c + 1]) ++c;
     for (uint32_t w = 0; w < x.nwin; ++w) {
-      const uint64_t s = uint64_t(i) * x.nwin + w;
-      uint64_t lo = 0, hi = 0;
-      if (x.padded) {
-        const uint32_t cap = x.cls_cap[size_t(w) * 8 + c];
-        lo = x.cls_base[size_t(w) * 8 + c] + uint64_t(i - x.pop_off[c]) * cap;
-        hi = lo + cap;
-      } else {
-        lo = x.seg_ptr[s];
-        hi = x.seg_ptr[s + 1];
-      }
-      for (uint64_t e2 = lo; e2 < hi; ++e2) {
-        uint32_t post, dl;
-        int32_t wq;
-        if (comp && x.padded) {
-          const uint32_t r = x.rec4[e2];
-          post = (x.win_first + w) * x.win_size + (r & 1023u) - x.win_origin;
-          dl = (r >> 10) & 63u;
-          wq = int32_t(int16_t(uint16_t(r >> 16))) * 8;
-        } else if (comp) {
-          post = (x.win_first + w) * x.win_size + x.tgt16[e2] - x.win_origin;
-          dl = x.d8[e2];
-          wq = int32_t(x.w16[e2]) * 8;
+      for (uint32_t b = 0; b < (x.padded ? nb : 1u); ++b) {
+        uint64_t lo = 0, hi = 0;
+        if (x.padded) {
+          const size_t k = (size_t(w) * nb + b) * 8 + c;
+          const uint32_t cap = x.cls_cap[k];
+          lo = x.cls_base[k] + uint64_t(i - x.pop_off[c]) * cap;
+          hi = lo + cap;
         } else {
-          const uint32_t hiw = uint32_t(x.rec8[e2] >> 32);
-          post = hiw >> 6;
-          dl = hiw & 63u;
-          wq = int32_t(uint32_t(x.rec8[e2]));
+          const uint64_t s = uint64_t(i) * x.nwin + w;
+          lo = x.seg_ptr[s];
+          hi = x.seg_ptr[s + 1];
         }
-        if (dl == 0) continue;  // an unused slot of a padded segment
-        if (o >= x.nsyn) {
-          snn_free_network(n);
-          return fail(nullptr, SNN_E_RANGE, "storage holds more synapses than sampled");
+        for (uint64_t e2 = lo; e2 < hi; ++e2) {
+          uint32_t post, dl;
+          int32_t wq;
+          bool unused;
+          if (comp && x.band_h) {   // banded: weight << 16 | (delay - band_lo) << ob | offset
+            const uint32_t r = x.rec4[e2];
+            post = w * x.win_size + (r & ((1u << ob) - 1u));
+            dl = band_lo(b, x.band_h) + ((r & 0xFFFFu) >> ob);
+            wq = int32_t(int16_t(uint16_t(r >> 16))) * 8;
+            unused = wq == 0;
+          } else if (comp && x.padded) {
+            const uint32_t r = x.rec4[e2];
+            post = (x.win_first + w) * x.win_size + (r & 1023u) - x.win_origin;
+            dl = (r >> 10) & 63u;
+            wq = int32_t(int16_t(uint16_t(r >> 16))) * 8;
+            unused = dl == 0;
+          } else if (comp) {
+            post = (x.win_first + w) * x.win_size + x.tgt16[e2] - x.win_origin;
+            dl = x.d8[e2];
+            wq = int32_t(x.w16[e2]) * 8;
+            unused = false;
+          } else {
+            const uint32_t hiw = uint32_t(x.rec8[e2] >> 32);
+            post = hiw >> 6;
+            dl = hiw & 63u;
+            wq = int32_t(uint32_t(x.rec8[e2]));
+            unused = dl == 0;
+          }
+          if (unused) continue;  // an unused slot of a padded segment
+          if (o >= x.nsyn) {
+            snn_free_network(n);
+            return fail(nullptr, SNN_E_RANGE, "storage holds more synapses than sampled");
+          }
+          n->post[o] = post;
+          n->delay[o] = uint8_t(dl);
+          n->w_q[o] = wq;
+          ++o;
         }
-        n->post[o] = post;
-        n->delay[o] = uint8_t(dl);
-        n->w_q[o] = wq;
-        ++o;
       }
     }
   }
   n->row_ptr[x.n] = o;
   if (o != x.nsyn) {
     snn_free_network(n);
-    return fail(nullptr, SNN_E_RANGE, "storage holds %llu of %llu synapses",
-                (unsigned long long)o, (unsigned long long)x.nsyn);
+    return fail(nullptr, SNN_E_RANGE, "storage holds %llu of %llu synapses", (unsigned long long)o,
+                (unsigned long long)x.nsyn);
   }
   *out = n;
   return SNN_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int snn_sample_network_windows(const snn_instance_cfg *inst, uint32_t syn_format, uint32_t window,
+                               int32_t host_threads, snn_host_network **out) {
+  if (!inst || !out) return fail(nullptr, SNN_E_INVAL, "NULL argument");
+  *out = nullptr;
+  if (window != 0 && window != 256 && window != 512)
+    return fail(nullptr, SNN_E_INVAL, "window must be 0, 256 or 512");
+  HostInstance x;
+  std::string e;
+  uint32_t wsize = syn_format == SNN_SYN_COMPRESSED5 ? (1u << kTargetBlockBits) : kNoWindows;
+  if (window) wsize = window;
+  int rc = sample_instance(*inst, syn_format, wsize, 0, window != 0, host_threads, x, e);
+  if (rc) return fail(nullptr, rc, "%s", e.c_str());
+  return read_back(x, syn_format, out);
+}
+
+int snn_sample_network_bands(const snn_instance_cfg *inst, uint32_t syn_format, uint32_t window,
+                             uint32_t ring_rows, int32_t host_threads, snn_host_network **out) {
+  if (!inst || !out) return fail(nullptr, SNN_E_INVAL, "NULL argument");
+  *out = nullptr;
+  if (window < 4 || window > 4096 || window % 4)
+    return fail(nullptr, SNN_E_INVAL, "window must be a multiple of 4 in [4, 4096]");
+  if (ring_rows != 64 && ring_rows != 32 && ring_rows != 16 && ring_rows != 8)
+    return fail(nullptr, SNN_E_INVAL, "ring_rows must be 64, 32, 16 or 8");
+  HostInstance x;
+  std::string e;
+  int rc = sample_instance_banded(*inst, syn_format, window, ring_rows, host_threads, x, e);
+  if (rc) return fail(nullptr, rc, "%s", e.c_str());
+  return read_back(x, syn_format, out);
 }
 
 void snn_free_network(snn_host_network *n) {

@@ -64,6 +64,20 @@ SNN_HD inline Philox4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint3
   return Philox4{{c0, c1, c2, c3}};
 }
 
+// Delay bands of the banded LDS engine (Sec. 3.4, lst:horizon2, with the
+// one-step delays split off): with H ring rows, band 0 holds the synapses of
+// delay 1 and slow band j >= 1 those of delays [2 + (j-1) H, 1 + j H]
+// (clipped at 63).  A spike of step s is delivered band by band: band j at
+// step s + band_lo(j), when its rows all lie inside the H live rows.
+SNN_HD constexpr uint32_t band_count(uint32_t H) { return 1u + (62u + H - 1u) / H; }
+SNN_HD constexpr uint32_t band_lo(uint32_t j, uint32_t H) { return j == 0 ? 1u : 2u + (j - 1u) * H; }
+SNN_HD constexpr uint32_t band_of(uint32_t d, uint32_t H) { return d <= 1 ? 0u : 1u + (d - 2u) / H; }
+// Compressed banded records: weight (16 bits) << 16 | (delay - band_lo) << OB
+// | offset in the window (OB bits), OB = 16 - log2(H).
+SNN_HD constexpr uint32_t band_offset_bits(uint32_t H) {
+  return H >= 64 ? 10u : H >= 32 ? 11u : H >= 16 ? 12u : H >= 8 ? 13u : 0u;
+}
+
 // Per-instance table the kernels read (device memory, uniform per wave).
 struct InstDev {
   uint64_t seed;
@@ -111,6 +125,8 @@ struct HostInstance {
   // cls_base[w * 8 + c] + (s - pop_off[c]) * cls_cap[w * 8 + c]; unused
   // slots have delay 0.  outdeg[s] counts the sender's real synapses.
   bool padded = false;
+  uint32_t band_h = 0;               // banded layout: ring rows of the engine, else 0
+  uint32_t nband = 1;                // delay bands per (sender, window)
   std::vector<uint64_t> cls_base;
   std::vector<uint32_t> cls_cap;
   std::vector<uint32_t> outdeg;
@@ -144,6 +160,13 @@ extern const uint32_t kKext[8];
 int sample_instance(const snn_instance_cfg &cfg, uint32_t syn_format, uint32_t win_size,
                     uint32_t win_origin, bool pad, int threads, HostInstance &out,
                     std::string &err);
+// Banded layout (band.hip): windows of win_size neurons from the instance's
+// first neuron, segments per (sender, window, delay band) for a ring of
+// band_h rows; cls_cap / cls_base are indexed [(window * nband + band) * 8 +
+// class].  Plain records as above; compressed records weight << 16 | (delay -
+// band_lo) << band_offset_bits | offset in the window.
+int sample_instance_banded(const snn_instance_cfg &cfg, uint32_t syn_format, uint32_t win_size,
+                           uint32_t band_h, int threads, HostInstance &out, std::string &err);
 // Population sizes of an instance (for placement before sampling).
 uint32_t instance_neurons(const snn_instance_cfg &cfg);
 // Longest thalamic count table of an instance's populations.

@@ -21,6 +21,7 @@ ENGINE_AUTO = 0
 ENGINE_STEPWISE = 1
 ENGINE_PERSISTENT = 2
 ENGINE_LDS = 3
+ENGINE_BAND = 4
 ABI_VERSION = 2
 
 SNN_OK = 0
@@ -70,7 +71,7 @@ class _Info(C.Structure):
                 ("n_neurons_total", C.c_uint32), ("n_synapses_total", C.c_uint64),
                 ("device_bytes", C.c_uint64), ("build_seconds", C.c_double),
                 ("launches_per_chunk", C.c_uint32), ("window_neurons", C.c_uint32),
-                ("graphs", C.c_uint32), ("reserved", C.c_uint32)]
+                ("graphs", C.c_uint32), ("ring_rows", C.c_uint32)]
 
 
 class _Tune(C.Structure):
@@ -96,6 +97,7 @@ SIGNATURES = {
     "snn_read_spikes": (C.c_int, [C.c_void_p, C.c_uint32, C.c_uint64, C.c_uint64,
                                   C.POINTER(C.c_uint32), C.POINTER(C.c_uint32), C.c_uint64,
                                   C.POINTER(C.c_uint64)]),
+    "snn_discard_spikes": (C.c_int, [C.c_void_p, C.c_uint64]),
     "snn_read_state": (C.c_int, [C.c_void_p, C.c_uint32, C.POINTER(_State)]),
     "snn_destroy": (None, [C.c_void_p]),
     "snn_last_error": (C.c_char_p, [C.c_void_p]),
@@ -106,6 +108,8 @@ SIGNATURES = {
                                      C.POINTER(C.POINTER(_HostNet))]),
     "snn_sample_network_windows": (C.c_int, [C.POINTER(_Inst), C.c_uint32, C.c_uint32, C.c_int32,
                                              C.POINTER(C.POINTER(_HostNet))]),
+    "snn_sample_network_bands": (C.c_int, [C.POINTER(_Inst), C.c_uint32, C.c_uint32, C.c_uint32,
+                                           C.c_int32, C.POINTER(C.POINTER(_HostNet))]),
     "snn_free_network": (None, [C.POINTER(_HostNet)]),
 }
 
@@ -177,7 +181,7 @@ def _syn_format(fmt):
 def _engine(e):
     if isinstance(e, str):
         return {"auto": ENGINE_AUTO, "stepwise": ENGINE_STEPWISE, "persistent": ENGINE_PERSISTENT,
-                "lds": ENGINE_LDS}[e]
+                "lds": ENGINE_LDS, "band": ENGINE_BAND}[e]
     return int(e)
 
 
@@ -274,6 +278,11 @@ class Simulator:
                                      C.byref(n)), self.h)
         return steps, ids
 
+    def discard_spikes(self, t_before):
+        """Drop the stored spikes of steps before t_before (all instances)."""
+        _check(lib().snn_discard_spikes(self.h, int(t_before)), self.h)
+        return self
+
     def state(self, inst=0, ring=False):
         st = _State()
         _check(lib().snn_read_state(self.h, inst, C.byref(st)), self.h)
@@ -306,15 +315,20 @@ class Simulator:
         return {f: getattr(inf, f) for f, _ in _Info._fields_}
 
 
-def sample_network(instance: Instance, syn_format="plain", host_threads=0, window=0):
+def sample_network(instance: Instance, syn_format="plain", host_threads=0, window=0, ring_rows=0):
     """The network snn_build would upload, sampled on the host (no GPU).
-    window = 256 or 512 reads it back from the LDS engine's storage layout."""
+    window = 256 or 512 reads it back from the LDS engine's storage layout;
+    window > 0 with ring_rows (64, 32, 16, 8) from the banded engine's."""
     keep = []
     s = _Inst()
     instance.fill(s, keep)
     p = C.POINTER(_HostNet)()
-    _check(lib().snn_sample_network_windows(C.byref(s), _syn_format(syn_format), int(window),
-                                            int(host_threads), C.byref(p)))
+    if ring_rows:
+        _check(lib().snn_sample_network_bands(C.byref(s), _syn_format(syn_format), int(window),
+                                              int(ring_rows), int(host_threads), C.byref(p)))
+    else:
+        _check(lib().snn_sample_network_windows(C.byref(s), _syn_format(syn_format), int(window),
+                                                int(host_threads), C.byref(p)))
     try:
         net = p.contents
         n, m = net.n_neurons, net.n_synapses

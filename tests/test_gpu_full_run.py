@@ -1,0 +1,64 @@
+"""The full-scale microcircuit over the whole 10 s run, bit for bit.
+
+The int32 input sum makes the FP32 path deterministic (eqn:mem, eqn:psc and
+eqn:ref with one exact integer input per step), so the GPU must reproduce the
+int32 oracle's raster for all 100,000 steps, not only for a short window:
+Sec. 4.1 asks for spike-for-spike agreement with the reference arithmetic.
+The oracle's per-step fingerprints and final-state hashes are stored in
+golden/int32_full_scale_seed1*.{json,digest.gz} (written by
+golden/make_int32_digests.py from the oracle alone).  The GPU runs in the
+benchmark's launch configuration (10,000-step chunks) in both synapse
+formats; the first step whose fingerprint differs is reported."""
+import gzip
+import hashlib
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from spike_stats import first_digest_divergence, step_digest
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def say(*a):
+    print("[gpu-full-run]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def golden():
+    with open(os.path.join(GOLDEN, "int32_full_scale_seed1.json")) as f:
+        meta = json.load(f)
+    dig = {}
+    for fmt, m in meta["modes"].items():
+        with gzip.open(os.path.join(GOLDEN, m["digest_file"]), "rb") as f:
+            raw = f.read()
+        assert hashlib.sha256(raw).hexdigest() == m["digest_sha256"]
+        dig[fmt] = np.frombuffer(raw, dtype="<i8").reshape(-1, 3)
+    return meta, dig
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("fmt", ["plain", "compressed"])
+def test_full_scale_10s_bit_exact(golden, full_scale_runs, fmt):
+    meta, dig = golden
+    m = meta["modes"][fmt]
+    run = full_scale_runs[fmt]
+    say(fmt, "launch", run["info"])
+    assert run["info"]["chunk_steps"] == 10000
+    assert run["t"] == meta["steps"] == len(dig[fmt])
+    ours = step_digest(run["steps"], run["ids"], meta["steps"])
+    div = first_digest_divergence(ours, dig[fmt])
+    say(fmt, "spikes", len(run["ids"]), "oracle", m["n_spikes"], "first differing step", div)
+    assert div is None, f"raster differs from the oracle from step {div} on"
+    assert len(run["ids"]) == m["n_spikes"]
+    c = m["counters"]
+    for k in ("spikes", "events", "poisson", "consumed"):
+        assert run["counters"][k] == c[k], (k, run["counters"][k], c[k])
+    for k in ("U", "I", "R", "W"):
+        assert run["sha256"][k] == m["sha256"][k], f"final {k} differs from the oracle's"

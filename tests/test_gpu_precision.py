@@ -1,7 +1,7 @@
 """Precision of the FP32/int32 paths against the FP64 oracle (Sec. 4.1).
 
 The GPU paths reproduce their int32 oracles bit for bit (test_gpu_parity);
-here the plain path and the compressed form (16-bit weights, Sec. 5.1) are
+here the plain path and the compressed form (16-bit weights, Sec. 5.3) are
 compared with the FP64 oracle (FP64 state and propagators, unquantised
 weights), which they are not expected to match spike for spike.  Bar:
 population rates within 5 % and mean CV of inter-spike intervals within 0.05
@@ -40,15 +40,9 @@ def ref():
 
 
 @pytest.fixture(scope="module")
-def runs(ref):
-    import paper_2405_02019_amd as P
-    out = {}
-    for fmt in ["plain", "compressed"]:
-        say("full scale", fmt, ref["steps"], "steps")
-        with P.Simulator(P.Instance(scale=1.0, seed=ref["seed"]), syn_format=fmt) as sim:
-            sim.step(ref["steps"])
-            out[fmt] = sim.spikes()
-    return out
+def runs(ref, full_scale_runs):
+    assert ref["steps"] == 100000 and ref["seed"] == 1
+    return {fmt: (r["steps"], r["ids"]) for fmt, r in full_scale_runs.items()}
 
 
 @pytest.mark.timeout(600)

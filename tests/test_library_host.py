@@ -143,11 +143,57 @@ def test_windowed_layout_holds_the_oracle_network(P, oracle, window, fmt, wmode)
         P.sample_network(P.Instance(scale=0.01), fmt, window=100)
 
 
+@pytest.mark.parametrize("window,ring_rows", [(256, 64), (1000, 16), (2048, 8), (320, 32)])
+@pytest.mark.parametrize("fmt,wmode", [("plain", 0), ("compressed", 1)])
+def test_banded_layout_holds_the_oracle_network(P, oracle, window, ring_rows, fmt, wmode):
+    """The banded engine's layout (fixed-capacity segments per sender,
+    target window and delay band: delay 1, then bands of H delays from 2 on,
+    Sec. 3.4) read back gives every row of the oracle's network, as a
+    multiset, and nothing else; within a row, synapses come by window, then
+    by band, and every synapse sits in the band of its delay."""
+    scale, mode, seed = 0.04, 1, 4
+    a = P.sample_network(P.Instance(scale=scale, indegree_mode=mode, seed=seed), fmt, window=window,
+                         ring_rows=ring_rows)
+    net = oracle.Net(oracle.Config(scale=scale, indegree_mode=mode, seed=seed, weight_mode=wmode))
+    rp, post, d, w, wq = net.csr()
+    assert a["nsyn"] == net.nsyn
+    np.testing.assert_array_equal(a["row_ptr"], rp)
+    pre = np.repeat(np.arange(net.N), np.diff(rp).astype(np.int64))
+    k1 = np.lexsort((a["w_q"], a["delay"], a["post"], pre))
+    k2 = np.lexsort((wq, d, post, pre))
+    np.testing.assert_array_equal(a["post"][k1], post[k2])
+    np.testing.assert_array_equal(a["delay"][k1], d[k2])
+    np.testing.assert_array_equal(a["w_q"][k1], wq[k2])
+    dl = a["delay"].astype(np.int64)
+    band = np.where(dl <= 1, 0, 1 + (dl - 2) // ring_rows)
+    key = (a["post"].astype(np.int64) // window) * 64 + band
+    same_row = pre[1:] == pre[:-1]
+    assert np.all(key[1:][same_row] >= key[:-1][same_row])
+    assert band.max() <= (62 + ring_rows - 1) // ring_rows and band.max() >= 1
+
+
+def test_banded_layout_rejects_bad_shapes(P):
+    inst = P.Instance(scale=0.01)
+    for window, rows in [(0, 16), (4098, 16), (255, 64), (256, 12), (256, 128)]:
+        with pytest.raises(P.SnnError, match="INVAL"):
+            P.sample_network(inst, "plain", window=window, ring_rows=rows)
+    # compressed offsets take 16 - log2(H) bits: 1,024 neurons at H = 64
+    with pytest.raises(P.SnnError, match="RANGE"):
+        P.sample_network(inst, "compressed", window=2048, ring_rows=64)
+
+
 def test_sampler_independent_of_thread_count(P):
     a = P.sample_network(P.Instance(scale=0.05, seed=2), "plain", host_threads=1)
     b = P.sample_network(P.Instance(scale=0.05, seed=2), "plain", host_threads=7)
     for k in ["row_ptr", "post", "delay", "w_q", "u0"]:
         np.testing.assert_array_equal(a[k], b[k])
+    for fmt in ["plain", "compressed"]:
+        a = P.sample_network(P.Instance(scale=0.05, seed=2), fmt, host_threads=1, window=700,
+                             ring_rows=16)
+        b = P.sample_network(P.Instance(scale=0.05, seed=2), fmt, host_threads=5, window=700,
+                             ring_rows=16)
+        for k in ["row_ptr", "post", "delay", "w_q", "u0"]:
+            np.testing.assert_array_equal(a[k], b[k])
 
 
 def test_sampler_error_paths(P):

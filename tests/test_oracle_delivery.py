@@ -60,6 +60,67 @@ def pull_simulation(net, T_rec, n_steps):
     return np.array(raster, dtype=np.int64).reshape(-1, 2), np.array(inputs), U, I, R
 
 
+def pull_simulation_f64(net, T_rec, n_steps):
+    """lst:pull in numpy float64 with the unquantised weights and FP64
+    propagators from the continuous solution: the FP64 oracle's arithmetic
+    up to the order of summation of a step's input."""
+    row_ptr, post, delay, w, wq = net.csr()
+    N = net.N
+    pre = np.repeat(np.arange(N), np.diff(row_ptr).astype(np.int64))
+    Wd = np.zeros((64, N, N), np.float64)         # [delay][receiver][sender]
+    np.add.at(Wd, (delay.astype(np.int64), post.astype(np.int64), pre), w)
+    p11, p22, p21 = math.exp(-DT / TAU_S), math.exp(-DT / TAU_M), kernel_u(DT)
+    w_ext = 0.15 / kernel_u(math.log(TAU_M / TAU_S) * BETA)
+    U = net.u0_f64().copy()
+    I = np.zeros(N)
+    R = np.zeros(N, np.int64)
+    hist, raster, inputs, margin = [], [], [], np.inf
+    for t in range(n_steps):
+        refr = R > 0
+        x = p22 * U + p21 * I
+        margin = min(margin, float(np.abs(x[~refr] - 15.0).min()) if (~refr).any() else np.inf)
+        spike = (~refr) & (x >= 15.0)
+        U = np.where(refr | spike, 0.0, x)
+        R = np.where(refr, R - 1, np.where(spike, 20, 0))
+        s = np.zeros(N)
+        for d in range(1, 64):
+            if t - d < 0:
+                break
+            src = hist[t - d]
+            if len(src):
+                s += Wd[d][:, src].sum(axis=1)
+        hist.append(np.nonzero(spike)[0])
+        raster.extend((t, i) for i in hist[-1])
+        inputs.append(s)
+        I = p11 * I + (T_rec[t] * w_ext + s)
+    return np.array(raster, dtype=np.int64).reshape(-1, 2), np.array(inputs), U, I, R, margin
+
+
+def test_f64_pull_brute_force_reproduces_push(oracle):
+    """The FP64 oracle (FP64 state, propagators and ring, unquantised
+    weights) against an FP64 pull brute force on the 1 % circuit: the same
+    raster spike for spike, and ring inputs and state equal up to the order
+    of the additions.  A step's input sums at most a few hundred weights of
+    at most ~1 nA, so a different order changes it by < 1e-9 pA; the state's
+    recursions contract (p11, p22 < 1), so they stay within 1e-9 as well.
+    Decisions flip only for a membrane value within that error of the
+    threshold; the run's closest approach is reported and must be far
+    larger."""
+    net = oracle.Net(oracle.Config(scale=0.01, seed=3))
+    sim = oracle.Sim(net, arith=oracle.ARITH_F64, record_inputs=True).run(1500)
+    T_rec, w_rec = sim.recorded_inputs()
+    raster, inputs, U, I, R, margin = pull_simulation_f64(net, T_rec, 1500)
+    steps, ids = sim.raster()
+    assert len(steps) > 10000 and margin > 1e-7, margin
+    np.testing.assert_array_equal(raster[:, 0], steps)
+    np.testing.assert_array_equal(raster[:, 1], ids)
+    np.testing.assert_allclose(inputs, w_rec, rtol=0, atol=1e-9)
+    st = sim.state()
+    np.testing.assert_allclose(st["U"], U, rtol=0, atol=1e-9)
+    np.testing.assert_allclose(st["I"], I, rtol=0, atol=1e-9)
+    np.testing.assert_array_equal(st["R"], R)
+
+
 @pytest.fixture(scope="module")
 def tiny(oracle):
     net = oracle.Net(oracle.Config(scale=0.01, seed=3))

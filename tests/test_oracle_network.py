@@ -36,6 +36,25 @@ def test_full_scale_counts(oracle):
     assert n[1, 4] == pytest.approx(g["value"], rel=g["rel_tol"])
 
 
+def test_table_orientation_against_the_spiking_count():
+    """Sec. 3.3 reports that on average 23 neurons of the full-scale circuit
+    spike per step.  The int32 oracle's full-scale run (stored by
+    golden/make_orientation.py from the oracle alone) gives about 25 with
+    the table's rows as target populations -- the reading taken -- and about
+    75 with rows as sources, three times the paper's figure; the chosen
+    reading also keeps every population active (the transposed one silences
+    L23e)."""
+    with open(os.path.join(HERE, "golden", "orientation_full_scale.json")) as f:
+        got = json.load(f)["readings"]
+    target = GOLD["mean_spikers_per_step"]["value"]
+    chosen = got["rows_are_targets"]["spikes_per_step"]
+    other = got["rows_are_sources"]["spikes_per_step"]
+    assert abs(chosen / target - 1.0) < 0.15, chosen
+    assert abs(other / target - 1.0) > 1.0, other
+    assert min(got["rows_are_targets"]["rates_hz"]) > 0.5
+    assert min(got["rows_are_sources"]["rates_hz"]) < 0.1
+
+
 def test_fixed_total_rule_realises_the_probability(oracle):
     """n synapses drawn with replacement over N_pre N_post pairs connect a
     given pair with probability 1 - (1 - 1/(N_pre N_post))^n, which must be
