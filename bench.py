@@ -56,12 +56,19 @@ def algorithmic_bytes(n_neurons, spikes, events, rec_bytes):
     return 8.0 * n_neurons, (rec_bytes + 4.0) * events + 24.0 * spikes
 
 
-def run_leg(P, instances, fmt, engine, chunk, warm_bio_s, timed_bio_s, log):
+def run_leg(P, instances, fmt, engine, chunk, warm_bio_s, timed_bio_s, log, tune_steps=0,
+            tune_cache=None):
     import torch
     t_build = time.perf_counter()
-    sim = P.Simulator(instances, syn_format=fmt, engine=engine, chunk_steps=chunk)
+    sim = P.Simulator(instances, syn_format=fmt, engine=engine, chunk_steps=chunk,
+                      tune_steps=tune_steps, tune_cache=tune_cache)
     build_s = time.perf_counter() - t_build
     info = sim.info()
+    layout = sim.tune_report
+    if layout:
+        log(f"[bench] {fmt}: layout tuned over {layout['candidates']} candidates (0 = cached): "
+            f"engine {layout['engine']}, window {layout['window_neurons']}, "
+            f"{layout['us_per_step_first']:.2f} -> {layout['us_per_step_best']:.2f} us/step")
     log(f"[bench] {fmt}: built in {build_s:.1f} s ({info['n_synapses_total']} synapses, "
         f"engine {info['engine']}, block {info['block_size']}, grid {info['grid_blocks']}, "
         f"window {info['window_neurons']}, ring rows {info['ring_rows']}, "
@@ -106,6 +113,7 @@ def run_leg(P, instances, fmt, engine, chunk, warm_bio_s, timed_bio_s, log):
         "fmt": fmt, "wall_s": wall, "gpu_ms": gpu_ms, "events": events, "spikes": spikes,
         "n_steps": n_steps, "n_neurons": n, "build_s": build_s, "info": info,
         "bytes": total_bytes, "launches": launches, "rec_bytes": rec, "tune": tune,
+        "layout": layout,
     }
 
 
@@ -212,7 +220,7 @@ def leg_summary(P, leg, bio, workload):
             "device_bytes": info["device_bytes"], "engine": info["engine"],
             "block": info["block_size"], "grid": info["grid_blocks"],
             "window_neurons": info["window_neurons"], "ring_rows": info["ring_rows"],
-            "roofline": roofline(P, leg, workload)}
+            "layout_tuning": leg["layout"], "roofline": roofline(P, leg, workload)}
 
 
 def run_workload(P, workloads, name, args, log, bio_steps=None):
@@ -221,8 +229,8 @@ def run_workload(P, workloads, name, args, log, bio_steps=None):
     instances = workloads.WORKLOADS[name]()
     legs = [f for f in wl["legs"] if not (f == "compressed" and args.no_compressed)
             and not (f == "plain" and args.no_plain)] or wl["legs"][:1]
-    return bio, instances, [run_leg(P, instances, f, args.engine, args.chunk, args.warmup, bio, log)
-                            for f in legs]
+    return bio, instances, [run_leg(P, instances, f, args.engine, args.chunk, args.warmup, bio, log,
+                                    args.tune_steps, args.tune_cache) for f in legs]
 
 
 def main():
@@ -238,6 +246,11 @@ def main():
     ap.add_argument("--no-plain", action="store_true", help="skip the plain-synapse legs")
     ap.add_argument("--no-extra", action="store_true",
                     help="with the full workload: skip the batch and x4 workloads")
+    ap.add_argument("--tune-steps", type=int, default=2000,
+                    help="LDS engines: steps timed per candidate layout when the tuning cache has "
+                         "no entry for the workload (0 = no layout tuning)")
+    ap.add_argument("--tune-cache", default=os.path.join(ROOT, "paper_2405_02019_amd", "tune_cache.txt"),
+                    help="file of earlier layout choices (read; a miss appends)")
     ap.add_argument("--cpu-steps", type=int, default=10000,
                     help="oracle steps for the CPU baseline, full workload only (0 = skip)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -291,7 +304,8 @@ def main():
                    "window_neurons": info["window_neurons"], "ring_rows": info["ring_rows"],
                    "chunk_steps": info["chunk_steps"],
                    "launches_per_chunk": info["launches_per_chunk"], "graphs": info["graphs"],
-                   "autotuned": first["tune"] is not None},
+                   "autotuned": first["tune"] is not None or first["layout"] is not None,
+                   "layout_tuning": first["layout"]},
         "rtf": first["wall_s"] / bio,
         "bio_per_wall": bio / first["wall_s"],
         "spikes_per_step": first["spikes"] / first["n_steps"],

@@ -33,7 +33,7 @@
 extern "C" {
 #endif
 
-#define SNN_ABI_VERSION 2u
+#define SNN_ABI_VERSION 3u
 
 enum snn_status {
   SNN_OK = 0,
@@ -110,6 +110,9 @@ typedef struct {
   uint64_t raster_capacity;    /* device raster entries between drains; 0 = auto */
   int32_t host_threads;        /* threads of the network sampler; 0 = auto       */
   int32_t use_graphs;          /* 1: replay chunks from a captured HIP graph     */
+  uint32_t window_neurons;     /* LDS engines: neurons per window (a multiple of
+                                  4); 0 = the shortest that fills one launch     */
+  uint32_t reserved0;          /* 0                                              */
   void *hip_stream;            /* hipStream_t; NULL = a stream of the library    */
   void *(*dev_alloc)(size_t bytes, void *ctx); /* NULL = hipMalloc              */
   void (*dev_free)(void *ptr, void *ctx);
@@ -244,11 +247,11 @@ int snn_get_info(const snn_net *h, snn_info *out);
 /* ---- launch-shape tuning ----------------------------------------------- */
 typedef struct {
   uint32_t engine;
-  uint32_t candidates;        /* shapes timed                                  */
+  uint32_t candidates;        /* shapes timed (0: taken from the tuning cache) */
   uint32_t block_size;        /* shape adopted                                 */
   uint32_t grid_blocks;
   uint32_t quads_per_thread;
-  uint32_t reserved;
+  uint32_t window_neurons;    /* LDS engines: window length adopted            */
   double us_per_step_first;   /* the handle's shape before tuning              */
   double us_per_step_best;    /* the adopted shape                             */
 } snn_tune_report;
@@ -264,6 +267,23 @@ typedef struct {
  * Errors: as snn_step_n; SNN_E_INVAL for trial_steps = 0 or a NULL argument.
  */
 int snn_autotune(snn_net *h, uint32_t trial_steps, snn_tune_report *out);
+
+/*
+ * snn_build_tuned -- snn_build with the storage layout chosen by timing: for
+ * the LDS engines (engine AUTO, LDS or BAND) each candidate -- the engine
+ * (LDS, or banded with its ring rows) and the window length (the shortest
+ * that fills one launch, and longer ones up to the kernel's capacity: fewer,
+ * larger destination classes of Sec. 3.6) -- is built, run for trial_steps / 4
+ * warm-up and trial_steps timed steps, and the fastest is built again from
+ * step 0 and returned in *out.  Results do not depend on the choice.
+ *   cache_path: NULL, or a text file of earlier choices keyed by the GPU's
+ *   architecture name and a digest of the configuration; a hit builds the
+ *   cached choice without timing (rep->candidates = 0), a miss appends the
+ *   new choice.  Other engines: as snn_build (no candidates).
+ * Errors: as snn_build and snn_step_n; SNN_E_INVAL for trial_steps = 0.
+ */
+int snn_build_tuned(const snn_config *cfg, uint32_t trial_steps, const char *cache_path,
+                    snn_net **out, snn_tune_report *rep);
 
 /*
  * snn_time_steps -- queue n_steps steps (as snn_step_n) between two HIP events

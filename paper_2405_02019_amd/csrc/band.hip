@@ -160,7 +160,7 @@ struct BandWalk {
         cap = __shfl(cap_l, int(k & 63u));
         rbv[u] = __shfl(rb_l, int(k & 63u));
         cap = k < 64u ? cap : 0u;
-        addr = ((uint64_t(bhi) << 32) | blo) + off;
+        addr = join64(bhi, blo) + off;
       } else {
         // The piece's sender is the last lane whose first piece is <= U
         // (lanes past the last sender have p_l = nu > U).
@@ -169,8 +169,8 @@ struct BandWalk {
         cap = __builtin_amdgcn_readlane(cap_l, s);
         rbv[u] = __builtin_amdgcn_readlane(rb_l, s);
         off = 64u * k + lane;
-        addr = ((uint64_t(__builtin_amdgcn_readlane(uint32_t(base_l >> 32), s)) << 32) |
-                __builtin_amdgcn_readlane(uint32_t(base_l), s)) + off;
+        addr = join64(uint32_t(__builtin_amdgcn_readlane(uint32_t(base_l >> 32), s)),
+                      uint32_t(__builtin_amdgcn_readlane(uint32_t(base_l), s))) + off;
       }
       const bool ok = off < cap;
       if (COMP) {

@@ -84,6 +84,14 @@ __device__ __forceinline__ void wave_compact(uint32_t flags, uint32_t &lane_off,
 
 __device__ __forceinline__ float4 ld4(const float *p) { return *reinterpret_cast<const float4 *>(p); }
 
+// A 64-bit value from its two 32-bit halves.  The lane builtins return int:
+// their results must reach here as uint32_t, or a low half with bit 31 set
+// is sign-extended over the high half (record indices of networks with more
+// than 2^31 record slots).
+__device__ __forceinline__ uint64_t join64(uint32_t hi, uint32_t lo) {
+  return (uint64_t(hi) << 32) | uint64_t(lo);
+}
+
 __device__ __forceinline__ uint32_t ld_ag(const uint32_t *p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }

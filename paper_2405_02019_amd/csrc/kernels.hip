@@ -897,8 +897,8 @@ struct SegmentWalk {
       const uint32_t s = uint32_t(__popcll(__ballot(int(p_l <= P)))) - 1u;
       const uint32_t k = P - __builtin_amdgcn_readlane(p_l, s);
       const uint32_t cap = __builtin_amdgcn_readlane(cap_l, s);
-      const uint64_t base = ((uint64_t(__builtin_amdgcn_readlane(uint32_t(base_l >> 32), s)) << 32) |
-                             __builtin_amdgcn_readlane(uint32_t(base_l), s)) + 64u * k;
+      const uint64_t base = join64(uint32_t(__builtin_amdgcn_readlane(uint32_t(base_l >> 32), s)),
+                                   uint32_t(__builtin_amdgcn_readlane(uint32_t(base_l), s))) + 64u * k;
       const bool ok = 64u * k + lane < cap;
       if (COMP)
         r4[u] = ok ? __builtin_nontemporal_load(d.rec4 + base + lane) : 0u;

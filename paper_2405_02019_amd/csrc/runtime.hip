@@ -55,6 +55,7 @@ struct snn_net {
   bool dead = false;
   std::vector<uint2> lds_groups;    // LDS engine: launches (first window, windows)
   uint32_t band_variant = 0;        // banded engine: kernel variant (kBandVariants)
+  int device = 0;                   // the GPU the handle lives on
   std::string err;
   double build_seconds = 0.0;
 };
@@ -298,8 +299,8 @@ bool make_plan(const std::vector<InstMeta> &im, uint32_t L, uint32_t wn, uint32_
   return true;
 }
 
-int plan_lds(const std::vector<InstMeta> &im, uint32_t block, uint32_t grid, LdsPlan &p,
-             std::string &why) {
+int plan_lds(const std::vector<InstMeta> &im, uint32_t block, uint32_t grid, uint32_t want_L,
+             bool allow_groups, LdsPlan &p, std::string &why) {
   if (block && block != 256) {
     why = "the LDS engine runs 256-thread blocks";
     return SNN_E_INVAL;
@@ -307,6 +308,16 @@ int plan_lds(const std::vector<InstMeta> &im, uint32_t block, uint32_t grid, Lds
   const int g320 = lds_max_grid(320), g512 = lds_max_grid(512);
   if (g320 <= 0 || g512 <= 0) {
     why = "the LDS kernel cannot be made co-resident on this device";
+    return SNN_E_RANGE;
+  }
+  if (want_L) {   // the requested window length
+    const uint32_t L = want_L & ~3u;
+    const uint32_t wn = L <= 320 ? 320 : 512;
+    const uint32_t maxg = uint32_t(wn == 320 ? g320 : g512);
+    if (L >= 4 && L <= 512 && make_plan(im, L, wn, maxg, p) && p.groups.size() == 1 &&
+        (!grid || p.total == grid))
+      return SNN_OK;
+    why = "the requested window length does not fit one launch of the LDS engine";
     return SNN_E_RANGE;
   }
   if (grid) {   // exactly `grid` windows in one launch
@@ -326,9 +337,11 @@ int plan_lds(const std::vector<InstMeta> &im, uint32_t block, uint32_t grid, Lds
     if (4 * nq > uint64_t(maxg) * L) continue;
     if (make_plan(im, L, wn, maxg, p) && p.groups.size() == 1) return SNN_OK;
   }
-  // Networks beyond one co-resident grid would need several launches per
-  // chunk; that path is switched off (a run of a 64-instance batch in five
-  // launches per chunk faulted the GPU and its cause is not established).
+  // Networks beyond one co-resident grid: groups of whole instances at
+  // 512-neuron windows, launched one after another (only when the LDS engine
+  // is requested; the automatic choice prefers the banded engine's single
+  // launch).
+  if (allow_groups && make_plan(im, 512, 512, uint32_t(g512), p)) return SNN_OK;
   why = "the network needs more windows than one co-resident launch of the LDS engine holds";
   return SNN_E_RANGE;
 }
@@ -336,8 +349,8 @@ int plan_lds(const std::vector<InstMeta> &im, uint32_t block, uint32_t grid, Lds
 // Banded engine plan: the first kernel variant (by window capacity) and the
 // shortest window (at least 256 neurons) that put every instance into one
 // co-resident launch; a requested grid size fixes the number of windows.
-int plan_band(const std::vector<InstMeta> &im, uint32_t block, uint32_t grid, LdsPlan &p,
-              uint32_t &variant, std::string &why) {
+int plan_band(const std::vector<InstMeta> &im, uint32_t block, uint32_t grid, uint32_t want_L,
+              LdsPlan &p, uint32_t &variant, std::string &why) {
   uint64_t nq = 0;
   for (const InstMeta &m : im) nq += quads_of(m);
   for (uint32_t v = 0; v < kNumBandVariants; ++v) {
@@ -346,6 +359,15 @@ int plan_band(const std::vector<InstMeta> &im, uint32_t block, uint32_t grid, Ld
     const int g = band_max_grid(v);
     if (g <= 0) continue;
     const uint32_t maxg = uint32_t(g);
+    if (want_L) {   // the requested window length, with the first variant holding it
+      const uint32_t L = want_L & ~3u;
+      if (L >= 4 && L <= bv.wn && make_plan(im, L, bv.wn, maxg, p) && p.groups.size() == 1 &&
+          (!grid || p.total == grid)) {
+        variant = v;
+        return SNN_OK;
+      }
+      continue;
+    }
     if (grid) {
       for (uint32_t L = bv.wn; L >= 4; L -= 4)
         if (make_plan(im, L, bv.wn, maxg, p) && p.groups.size() == 1 && p.total == grid) {
@@ -423,6 +445,7 @@ int queue_steps(snn_net *h, uint32_t n) {
   return SNN_OK;
 }
 
+
 }  // namespace
 
 extern "C" {
@@ -481,6 +504,10 @@ int snn_build(const snn_config *cfg, snn_net **out) {
 
   snn_net *h = new snn_net();
   h->cfg = *cfg;
+  if (hipGetDevice(&h->device) != hipSuccess) {
+    delete h;
+    return fail(nullptr, SNN_E_HIP, "no current HIP device");
+  }
   h->cfg.inst = nullptr;
   h->chunk = cfg->chunk_steps ? cfg->chunk_steps : 100;
   auto bail = [&](int rc) {
@@ -529,9 +556,11 @@ int snn_build(const snn_config *cfg, snn_net **out) {
                     kLdsTab, tab);
       why = b;
     } else if (h->engine == SNN_ENGINE_LDS) {
-      prc = plan_lds(h->im, cfg->block_size, cfg->grid_blocks, plan, why);
+      prc = plan_lds(h->im, cfg->block_size, cfg->grid_blocks, cfg->window_neurons,
+                     cfg->engine == SNN_ENGINE_LDS, plan, why);
     } else {
-      prc = plan_band(h->im, cfg->block_size, cfg->grid_blocks, plan, h->band_variant, why);
+      prc = plan_band(h->im, cfg->block_size, cfg->grid_blocks, cfg->window_neurons, plan,
+                      h->band_variant, why);
     }
     if (prc == SNN_OK) {
       lds_window = plan.wn;
@@ -1124,7 +1153,169 @@ int snn_autotune(snn_net *h, uint32_t trial_steps, snn_tune_report *out) {
   out->block_size = h->shape.block;
   out->grid_blocks = h->engine == SNN_ENGINE_STEPWISE ? h->shape.scatter_blocks : h->shape.grid;
   out->quads_per_thread = h->shape.qpt;
+  for (const auto &m : h->im) out->window_neurons = std::max(out->window_neurons, m.wlen);
   out->us_per_step_best = best;
+  return SNN_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+struct TuneCand {
+  uint32_t engine, L;
+};
+
+// Candidate layouts of the LDS engines for a configuration: per engine the
+// shortest window that fills one launch, and longer ones (x 1.25, x 1.6) as
+// far as a kernel variant holds them.
+std::vector<TuneCand> tune_candidates(const snn_config *cfg) {
+  std::vector<InstMeta> im(cfg->n_instances);
+  for (uint32_t k = 0; k < cfg->n_instances; ++k) im[k].n = instance_neurons(cfg->inst[k]);
+  std::vector<TuneCand> out;
+  auto family = [&](uint32_t eng) {
+    LdsPlan p;
+    std::string why;
+    uint32_t v = 0;
+    const int rc = eng == SNN_ENGINE_LDS
+                       ? plan_lds(im, cfg->block_size, cfg->grid_blocks, 0, false, p, why)
+                       : plan_band(im, cfg->block_size, cfg->grid_blocks, 0, p, v, why);
+    if (rc) return;
+    uint32_t L0 = 0;
+    for (uint32_t wq : p.wq) L0 = std::max(L0, 4 * wq);
+    std::vector<uint32_t> seen;
+    for (double f : {1.0, 1.25, 1.6}) {
+      const uint32_t L = uint32_t(L0 * f + 3.0) & ~3u;
+      const int ok = eng == SNN_ENGINE_LDS
+                         ? plan_lds(im, cfg->block_size, cfg->grid_blocks, L, false, p, why)
+                         : plan_band(im, cfg->block_size, cfg->grid_blocks, L, p, v, why);
+      if (ok != SNN_OK || std::find(seen.begin(), seen.end(), p.total) != seen.end()) continue;
+      seen.push_back(p.total);
+      out.push_back({eng, L});
+    }
+  };
+  if (cfg->engine == SNN_ENGINE_AUTO || cfg->engine == SNN_ENGINE_LDS) family(SNN_ENGINE_LDS);
+  if (cfg->engine == SNN_ENGINE_AUTO || cfg->engine == SNN_ENGINE_BAND) family(SNN_ENGINE_BAND);
+  return out;
+}
+
+// FNV-1a digest of everything in a configuration that shapes the network and
+// its step loop.
+uint64_t config_digest(const snn_config *cfg) {
+  uint64_t h = 1469598103934665603ull;
+  auto mix = [&](const void *p, size_t n) {
+    const unsigned char *b = static_cast<const unsigned char *>(p);
+    for (size_t i = 0; i < n; ++i) h = (h ^ b[i]) * 1099511628211ull;
+  };
+  mix(&cfg->n_instances, 4);
+  mix(&cfg->syn_format, 4);
+  mix(&cfg->engine, 4);
+  mix(&cfg->block_size, 4);
+  mix(&cfg->grid_blocks, 4);
+  mix(&cfg->chunk_steps, 4);
+  for (uint32_t k = 0; k < cfg->n_instances; ++k) {
+    const snn_instance_cfg &c = cfg->inst[k];
+    mix(&c.seed, 8);
+    mix(&c.scale, 8);
+    mix(&c.indegree_mode, 4);
+    mix(&c.count_rule, 4);
+    mix(&c.rows_are_sources, 4);
+    mix(&c.g, 8);
+    mix(&c.bg_rate_hz, 8);
+    mix(&c.psp_ext_mv, 8);
+    mix(&c.bg_const_T, 4);
+    if (c.conn) mix(c.conn, 64 * sizeof(double));
+  }
+  return h;
+}
+
+}  // namespace
+
+extern "C" {
+
+int snn_build_tuned(const snn_config *cfg, uint32_t trial_steps, const char *cache_path,
+                    snn_net **out, snn_tune_report *rep) {
+  if (!out || !rep) return fail(nullptr, SNN_E_INVAL, "NULL argument");
+  *out = nullptr;
+  std::memset(rep, 0, sizeof *rep);
+  if (!trial_steps) return fail(nullptr, SNN_E_INVAL, "trial_steps must be positive");
+  if (!cfg || !cfg->inst || cfg->n_instances < 1 || cfg->n_instances > kMaxInstances)
+    return fail(nullptr, SNN_E_INVAL, "bad configuration");
+  snn_config c = *cfg;
+  const std::vector<TuneCand> cands =
+      cfg->window_neurons ? std::vector<TuneCand>() : tune_candidates(cfg);
+  if (cands.empty()) return snn_build(cfg, out);   // nothing to choose
+  int dev = 0;
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess)
+    return fail(nullptr, SNN_E_HIP, "no current HIP device");
+  char key[160];
+  std::snprintf(key, sizeof key, "%s %016llx", prop.gcnArchName,
+                (unsigned long long)config_digest(cfg));
+  TuneCand best{0, 0};
+  double best_us = 0.0, first_us = 0.0;
+  bool cached = false;
+  if (cache_path) {   // last matching line wins
+    if (FILE *f = std::fopen(cache_path, "r")) {
+      char line[256], arch[96], dig[32];
+      unsigned e = 0, L = 0;
+      double us = 0.0, us0 = 0.0;
+      while (std::fgets(line, sizeof line, f))
+        if (std::sscanf(line, "%95s %31s %u %u %lf %lf", arch, dig, &e, &L, &us, &us0) == 6 &&
+            std::strlen(key) == std::strlen(arch) + 1 + std::strlen(dig) &&
+            std::strncmp(key, arch, std::strlen(arch)) == 0 &&
+            std::strcmp(key + std::strlen(arch) + 1, dig) == 0) {
+          best = {e, L};
+          best_us = us;
+          first_us = us0;
+          cached = true;
+        }
+      std::fclose(f);
+    }
+  }
+  if (!cached) {
+    for (size_t i = 0; i < cands.size(); ++i) {
+      c.engine = cands[i].engine;
+      c.window_neurons = cands[i].L;
+      snn_net *h = nullptr;
+      int rc = snn_build(&c, &h);
+      if (rc) return rc;
+      double ms = 0.0;
+      rc = snn_step_n(h, std::max(1u, trial_steps / 4));
+      if (!rc) rc = snn_time_steps(h, trial_steps, &ms);
+      if (rc) {
+        g_build_error = h->err;
+        snn_destroy(h);
+        return rc;
+      }
+      snn_destroy(h);
+      const double us = 1000.0 * ms / trial_steps;
+      if (i == 0) first_us = us;
+      if (i == 0 || us < best_us) {
+        best_us = us;
+        best = cands[i];
+      }
+    }
+    if (cache_path) {
+      if (FILE *f = std::fopen(cache_path, "a")) {
+        std::fprintf(f, "%s %u %u %.4f %.4f\n", key, best.engine, best.L, best_us, first_us);
+        std::fclose(f);
+      }
+    }
+  }
+  c.engine = best.engine;
+  c.window_neurons = best.L;
+  const int rc = snn_build(&c, out);
+  if (rc) return rc;
+  const snn_net *h = *out;
+  rep->engine = h->engine;
+  rep->candidates = cached ? 0u : uint32_t(cands.size());
+  rep->block_size = h->shape.block;
+  rep->grid_blocks = h->shape.grid;
+  rep->quads_per_thread = h->shape.qpt;
+  for (const auto &m : h->im) rep->window_neurons = std::max(rep->window_neurons, m.wlen);
+  rep->us_per_step_first = first_us;
+  rep->us_per_step_best = best_us;
   return SNN_OK;
 }
 

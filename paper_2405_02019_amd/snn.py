@@ -22,7 +22,7 @@ ENGINE_STEPWISE = 1
 ENGINE_PERSISTENT = 2
 ENGINE_LDS = 3
 ENGINE_BAND = 4
-ABI_VERSION = 2
+ABI_VERSION = 3
 
 SNN_OK = 0
 ERRORS = {-1: "SNN_E_INVAL", -2: "SNN_E_NOMEM", -3: "SNN_E_HIP", -4: "SNN_E_RANGE",
@@ -52,6 +52,7 @@ class _Cfg(C.Structure):
                 ("chunk_steps", C.c_uint32), ("block_size", C.c_uint32),
                 ("grid_blocks", C.c_uint32), ("raster_capacity", C.c_uint64),
                 ("host_threads", C.c_int32), ("use_graphs", C.c_int32),
+                ("window_neurons", C.c_uint32), ("reserved0", C.c_uint32),
                 ("hip_stream", C.c_void_p), ("dev_alloc", _ALLOC), ("dev_free", _FREE),
                 ("alloc_ctx", C.c_void_p)]
 
@@ -77,7 +78,7 @@ class _Info(C.Structure):
 class _Tune(C.Structure):
     _fields_ = [("engine", C.c_uint32), ("candidates", C.c_uint32), ("block_size", C.c_uint32),
                 ("grid_blocks", C.c_uint32), ("quads_per_thread", C.c_uint32),
-                ("reserved", C.c_uint32), ("us_per_step_first", C.c_double),
+                ("window_neurons", C.c_uint32), ("us_per_step_first", C.c_double),
                 ("us_per_step_best", C.c_double)]
 
 
@@ -103,6 +104,8 @@ SIGNATURES = {
     "snn_last_error": (C.c_char_p, [C.c_void_p]),
     "snn_get_info": (C.c_int, [C.c_void_p, C.POINTER(_Info)]),
     "snn_time_steps": (C.c_int, [C.c_void_p, C.c_uint64, C.POINTER(C.c_double)]),
+    "snn_build_tuned": (C.c_int, [C.POINTER(_Cfg), C.c_uint32, C.c_char_p, C.POINTER(C.c_void_p),
+                                  C.POINTER(_Tune)]),
     "snn_autotune": (C.c_int, [C.c_void_p, C.c_uint32, C.POINTER(_Tune)]),
     "snn_sample_network": (C.c_int, [C.POINTER(_Inst), C.c_uint32, C.c_int32,
                                      C.POINTER(C.POINTER(_HostNet))]),
@@ -190,7 +193,10 @@ class Simulator:
 
     def __init__(self, instances, syn_format="plain", engine="auto", chunk_steps=100,
                  use_graphs=True, block_size=0, grid_blocks=0, raster_capacity=0,
-                 host_threads=0, device=0):
+                 host_threads=0, device=0, window_neurons=0, tune_steps=0, tune_cache=None):
+        """tune_steps > 0 builds through snn_build_tuned (the LDS engines' layout
+        chosen by timing that many steps per candidate; tune_cache: a file of
+        earlier choices); the report is kept in self.tune_report."""
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("no GPU: the simulator runs only on an MI355X (gfx950)")
@@ -232,12 +238,21 @@ class Simulator:
         cfg.grid_blocks = int(grid_blocks)
         cfg.raster_capacity = int(raster_capacity)
         cfg.host_threads = int(host_threads)
+        cfg.window_neurons = int(window_neurons)
         cfg.hip_stream = C.c_void_p(self.stream.cuda_stream)
         cfg.dev_alloc = self._alloc_cb
         cfg.dev_free = self._free_cb
         h = C.c_void_p()
+        self.tune_report = None
         with torch.cuda.device(self.device):
-            _check(lib().snn_build(C.byref(cfg), C.byref(h)))
+            if tune_steps:
+                rep = _Tune()
+                cache = tune_cache.encode() if tune_cache else None
+                _check(lib().snn_build_tuned(C.byref(cfg), int(tune_steps), cache, C.byref(h),
+                                             C.byref(rep)))
+                self.tune_report = {f: getattr(rep, f) for f, _ in _Tune._fields_}
+            else:
+                _check(lib().snn_build(C.byref(cfg), C.byref(h)))
         self.h = h
 
     def close(self):

@@ -294,14 +294,11 @@ def test_band_batched_instances(P, oracle, block):
                 assert_parity(sim, k, net, osim)
 
 
-@pytest.mark.skip(reason="LDS runs in several launches per chunk are switched off: a 64-instance "
-                         "batch run in five launches per chunk (graph-captured) faulted the GPU; "
-                         "cause not established")
 def test_lds_instance_groups_bit_exact(P, oracle):
     """Instances beyond one co-resident grid (18 x 10 % circuits, 139k
-    neurons) run as several LDS launches per chunk, each instance still equal
-    to its own oracle run; with and without graph-captured chunks, across
-    ragged chunk pieces."""
+    neurons) run as several LDS launches per chunk (groups of whole
+    instances, requested explicitly), each instance still equal to its own
+    oracle run, across ragged chunk pieces."""
     rng = np.random.default_rng(5)
     insts = [P.Instance(scale=0.1, seed=40 + i, g=float(rng.uniform(-6, -3)),
                         bg_rate_hz=float(rng.uniform(6, 10))) for i in range(18)]
@@ -335,6 +332,31 @@ def test_autotune_keeps_results_bit_exact(P, oracle, engine):
         for k, inst in enumerate(insts):
             net, osim = run_oracle(oracle, inst, 0, total)
             assert_parity(sim, k, net, osim)
+
+
+def test_tuned_build_bit_exact_and_cached(P, oracle, tmp_path):
+    """snn_build_tuned times the LDS engines' candidate layouts (LDS and
+    banded engine, several window lengths), rebuilds the fastest from step 0
+    and records the choice; a second build of the same configuration takes
+    it from the cache without timing.  Either way the results equal the
+    oracle's."""
+    inst = P.Instance(scale=0.05, seed=41)
+    cache = str(tmp_path / "tune.txt")
+    with P.Simulator(inst, chunk_steps=100, tune_steps=200, tune_cache=cache) as sim:
+        rep = sim.tune_report
+        say("tuned build", rep, sim.info())
+        assert rep["candidates"] >= 3 and rep["us_per_step_best"] <= rep["us_per_step_first"]
+        assert rep["window_neurons"] == sim.info()["window_neurons"]
+        sim.step(300)
+        net, osim = run_oracle(oracle, inst, 0, 300)
+        assert_parity(sim, 0, net, osim)
+    assert len(open(cache).read().splitlines()) == 1
+    with P.Simulator(inst, chunk_steps=100, tune_steps=200, tune_cache=cache) as sim:
+        rep2 = sim.tune_report
+        assert rep2["candidates"] == 0 and rep2["window_neurons"] == rep["window_neurons"]
+        assert rep2["engine"] == rep["engine"]
+        sim.step(300)
+        assert_parity(sim, 0, net, osim)
 
 
 @pytest.fixture(scope="module")

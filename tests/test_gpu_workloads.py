@@ -4,13 +4,16 @@ the launch-shape tuner has run):
 
 * the batch of 64 independent instances of uneven scale (5-20 %), g,
   background rate and seed (576,807 neurons, 2.2e9 synapses): every
-  instance equals its own oracle run spike for spike, with its state;
+  instance equals its own oracle run spike for spike, with its state (the
+  banded engine's 1,024-thread variant, 8 ring rows);
 * the 4x circuit with full-scale in-degrees (308,676 neurons, 1.2e9
   synapses), whose 64-row ring exceeds the chip's LDS: the banded engine
   (Sec. 3.4's horizon with 16 ring rows) against the oracle.
 
-Each case builds the oracle network of the same configuration on the host
-(about 20 GB for the 4x circuit)."""
+Both networks hold more than 2^31 record slots, so these are also the
+regression tests of 64-bit record addressing.  Each case builds the oracle
+network of the same configuration on the host (about 40 GB for the 4x
+circuit)."""
 import sys
 
 import numpy as np
@@ -59,7 +62,7 @@ def test_batch_of_64_bit_exact(P, oracle, fmt, wmode):
     with P.Simulator(insts, syn_format=fmt, chunk_steps=10000) as sim:
         info = sim.info()
         say("batch info", info)
-        assert info["engine"] in (P.ENGINE_LDS, P.ENGINE_BAND)
+        assert info["engine"] == P.ENGINE_BAND
         rep = sim.autotune(50)
         say("batch autotune", rep)
         total = rep["candidates"] * 50 + 250
