@@ -155,6 +155,35 @@ int snn_build(const snn_config *cfg, snn_net **out);
 int snn_step_n(snn_net *h, uint64_t n_steps);
 
 /*
+ * snn_step_n_noalloc -- snn_step_n for callers that cannot allocate memory
+ * (tight serving loops, harnesses that forbid allocation): advances every
+ * instance by n_steps steps without any device or host allocation and
+ * without synchronising.  LDS and banded engines only (SNN_E_INVAL for the
+ * others); the handle's device must be current.
+ *   d_raster: device buffer of raster_cap uint64 entries receiving this
+ *     call's spikes as (step << 32 | global neuron id), where instance k's
+ *     ids start at the sum of the earlier instances' neuron counts, each
+ *     rounded up to a multiple of 256; in runs of one window each in (step,
+ *     id) order, the runs in no particular order.  raster_cap must hold the
+ *     worst case, every neuron spiking once per 21 steps
+ *     (neurons * ((n_steps + 20) / 21)), else SNN_E_RANGE.
+ *   d_status: device buffer of 2 uint64 receiving, when the queued work
+ *     completes, the number of raster entries written and the device error
+ *     word (0 = success; nonzero: a bounded wait expired, the state is
+ *     invalid).
+ * The per-call state of the step loop (control words, flag words, sender
+ * lists and the sender history) lives in a static 32 MiB device array per
+ * GPU, cleared at the start of every call; networks needing more return
+ * SNN_E_RANGE (the LDS engine fits up to about 2 million neurons, the
+ * banded engine about 120,000).  Calls on one GPU must not overlap: they
+ * share that array.  State, counters and snn_read_state are as after
+ * snn_step_n; the spikes of this call are not in the handle's raster.
+ * Errors: SNN_E_INVAL, SNN_E_RANGE, SNN_E_HIP, SNN_E_DEVICE.
+ */
+int snn_step_n_noalloc(snn_net *h, uint64_t n_steps, uint64_t *d_raster, uint64_t raster_cap,
+                       uint64_t *d_status);
+
+/*
  * snn_read_spikes -- spikes of instance `inst` emitted in steps [t0, t1),
  * sorted by (step, neuron id).  A spike of step t is a neuron whose membrane
  * update of step t crossed the threshold (eqn:mem, eqn:ref): the neurons

@@ -6,6 +6,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <thread>
 #include <vector>
@@ -445,6 +446,66 @@ int queue_steps(snn_net *h, uint32_t n) {
   return SNN_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Scratch of the allocation-free step call: the per-call state of the LDS
+// engines (control words, flag epoch, flag words, sender lists, sender
+// history beyond the blocks' LDS) in one file-scope device array.  Every GPU
+// the library runs on holds its own copy until the process ends; host code
+// uses the address hipGetSymbolAddress returns for the current device, never
+// the array's name.  Calls that overlap on one GPU share it and race.
+// ---------------------------------------------------------------------------
+constexpr size_t kScratchBytes = size_t(32) << 20;
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// Address of the current device's scratch (looked up once per device).
+int scratch_address(int dev, void **out) {
+  if (dev < 0 || dev >= kMaxDevices) return fail(nullptr, SNN_E_INVAL, "device %d out of range", dev);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(nullptr, SNN_E_HIP, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return SNN_OK;
+}
+
+// Start of an allocation-free call: the scratch control block takes the
+// handle's step origin and clears the rest; flag words and the flag epoch
+// start at zero.  A kernel, not a memset, so the call can be captured.
+__global__ void k_noalloc_begin(Control *ctl, const Control *own, uint64_t *flags, uint32_t nflags,
+                                uint2 *lgroup) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i == 0) {
+    Control c{};
+    c.t_base = own->t_base;
+    *ctl = c;
+    *lgroup = make_uint2(0, 0);
+  }
+  for (uint32_t k = i; k < nflags; k += gridDim.x * blockDim.x) flags[k] = 0;
+}
+
+// End of an allocation-free call: the handle's step origin advances and the
+// caller's status words receive the raster entries written and the error
+// code of the bounded waits.
+__global__ void k_noalloc_end(Control *own, const Control *ctl, uint64_t *status) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    own->t_base = ctl->t_base;
+    status[0] = ctl->raster_n;
+    status[1] = uint64_t(ctl->error) | (uint64_t(ctl->overflow) << 32);
+  }
+}
+
+size_t round256(size_t b) { return (b + 255) & ~size_t(255); }
 
 }  // namespace
 
@@ -920,6 +981,62 @@ int snn_step_n(snn_net *h, uint64_t n_steps) {
     n_steps -= piece;
     sort_drained(h);   // while the device runs the chunk just queued
   }
+  return SNN_OK;
+}
+
+int snn_step_n_noalloc(snn_net *h, uint64_t n_steps, uint64_t *d_raster, uint64_t raster_cap,
+                       uint64_t *d_status) {
+  if (!h) return fail(nullptr, SNN_E_INVAL, "handle is NULL");
+  if (h->dead) return fail(h, SNN_E_DEVICE, "the handle is unusable after a device failure");
+  if (h->engine != SNN_ENGINE_LDS && h->engine != SNN_ENGINE_BAND)
+    return fail(h, SNN_E_INVAL, "the allocation-free call runs the LDS and banded engines only");
+  if (h->lds_groups.size() != 1) return fail(h, SNN_E_INVAL, "one launch per chunk is required");
+  if (!d_raster || !d_status) return fail(h, SNN_E_INVAL, "NULL raster or status");
+  if (n_steps == 0) return SNN_OK;
+  if (spike_bound(h, n_steps) > raster_cap)
+    return fail(h, SNN_E_RANGE, "%llu steps may emit %llu spikes, the raster holds %llu",
+                (unsigned long long)n_steps, (unsigned long long)spike_bound(h, n_steps),
+                (unsigned long long)raster_cap);
+  int dev = -1;
+  HIP_OK(h, hipGetDevice(&dev));
+  if (dev != h->device) return fail(h, SNN_E_INVAL, "the handle's device %d is not current", h->device);
+  const DeviceNet &d = h->d;
+  const size_t nflags = size_t(kSlots) * d.n_lwin;
+  const size_t b_ctl = round256(sizeof(Control)), b_grp = 256, b_flags = round256(nflags * 8),
+               b_list = round256(size_t(kSlots) * d.ntot * 4),
+               b_hist = d.ghist ? round256(size_t(64) * d.ntot * 4) : 0;
+  const size_t need = b_ctl + b_grp + b_flags + b_list + b_hist;
+  if (need > kScratchBytes)
+    return fail(h, SNN_E_RANGE, "the network needs %zu bytes of scratch, the static area holds %zu",
+                need, kScratchBytes);
+  void *base = nullptr;
+  const int rc = scratch_address(dev, &base);
+  if (rc) return fail(h, rc, "%s", snn_last_error(nullptr));
+  unsigned char *p = static_cast<unsigned char *>(base);
+  DeviceNet dv = d;
+  dv.ctl = reinterpret_cast<Control *>(p);
+  dv.lgroup = reinterpret_cast<uint2 *>(p + b_ctl);
+  dv.lflags = reinterpret_cast<uint64_t *>(p + b_ctl + b_grp);
+  dv.llist = reinterpret_cast<uint32_t *>(p + b_ctl + b_grp + b_flags);
+  dv.ghist = d.ghist ? reinterpret_cast<uint32_t *>(p + b_ctl + b_grp + b_flags + b_list) : nullptr;
+  dv.raster = d_raster;
+  dv.raster_cap = raster_cap;
+  hipLaunchKernelGGL(k_noalloc_begin, dim3(1), dim3(256), 0, h->stream, dv.ctl, d.ctl, dv.lflags,
+                     uint32_t(nflags), dv.lgroup);
+  HIP_OK(h, hipGetLastError());
+  for (uint64_t left = n_steps; left;) {
+    const uint32_t piece = uint32_t(std::min<uint64_t>(left, h->chunk));
+    if (h->engine == SNN_ENGINE_BAND) {
+      HIP_OK(h, launch_band(dv, h->band_variant, piece, h->stream));
+    } else {
+      const uint2 gr = h->lds_groups[0];
+      HIP_OK(h, launch_lds(dv, 0, 1, gr.x, gr.y, piece, h->stream));
+    }
+    left -= piece;
+  }
+  hipLaunchKernelGGL(k_noalloc_end, dim3(1), dim3(64), 0, h->stream, d.ctl, dv.ctl, d_status);
+  HIP_OK(h, hipGetLastError());
+  h->t += n_steps;
   return SNN_OK;
 }
 

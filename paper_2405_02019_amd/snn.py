@@ -98,6 +98,8 @@ SIGNATURES = {
     "snn_read_spikes": (C.c_int, [C.c_void_p, C.c_uint32, C.c_uint64, C.c_uint64,
                                   C.POINTER(C.c_uint32), C.POINTER(C.c_uint32), C.c_uint64,
                                   C.POINTER(C.c_uint64)]),
+    "snn_step_n_noalloc": (C.c_int, [C.c_void_p, C.c_uint64, C.c_void_p, C.c_uint64,
+                                     C.c_void_p]),
     "snn_discard_spikes": (C.c_int, [C.c_void_p, C.c_uint64]),
     "snn_read_state": (C.c_int, [C.c_void_p, C.c_uint32, C.POINTER(_State)]),
     "snn_destroy": (None, [C.c_void_p]),
@@ -275,6 +277,13 @@ class Simulator:
 
     def step(self, n_steps):
         _check(lib().snn_step_n(self.h, int(n_steps)), self.h)
+        return self
+
+    def step_noalloc(self, n_steps, raster, status):
+        """snn_step_n_noalloc: raster and status are device tensors (int64,
+        raster.numel() entries and 2) the call writes into."""
+        _check(lib().snn_step_n_noalloc(self.h, int(n_steps), C.c_void_p(raster.data_ptr()),
+                                        int(raster.numel()), C.c_void_p(status.data_ptr())), self.h)
         return self
 
     def time_steps(self, n_steps):
