@@ -46,7 +46,10 @@ WORKLOADS = {
            "name": "4x PD microcircuit with full in-degrees, {neurons} neurons, {syn} synapses, "
                    "dt 0.1 ms"},
 }
-KERNEL_SOURCES = {"k_lds": "kernels.hip", "k_persistent": "kernels.hip", "k_band": "band.hip"}
+# Sources whose bytes (concatenated in this order) a committed counter record
+# must match: the kernel's file and the device helpers it includes.
+KERNEL_SOURCES = {"k_lds": ["kernels.hip", "device.hpp"], "k_persistent": ["kernels.hip", "device.hpp"],
+                  "k_band": ["band.hip", "device.hpp"]}
 
 
 def algorithmic_bytes(n_neurons, spikes, events, rec_bytes):
@@ -132,15 +135,17 @@ def kernel_name(P, info):
 def profile_record(kernel, workload, fmt, chunk):
     """The committed rocprofv3 counter summary of a kernel and workload
     (profiles/traffic_<kernel>_<workload>_<fmt>.json) -- only while the
-    kernel's source is the one the counters were taken on, for the same
+    kernel's sources are the ones the counters were taken on, for the same
     launch length."""
     import hashlib
     path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}_{fmt}.json")
     if not os.path.exists(path) or kernel not in KERNEL_SOURCES:
         return None
     rec = json.load(open(path))
-    src = os.path.join(ROOT, "paper_2405_02019_amd", "csrc", KERNEL_SOURCES[kernel])
-    if hashlib.sha256(open(src, "rb").read()).hexdigest() != rec["kernel_source_sha256"]:
+    sha = hashlib.sha256()
+    for f in KERNEL_SOURCES[kernel]:
+        sha.update(open(os.path.join(ROOT, "paper_2405_02019_amd", "csrc", f), "rb").read())
+    if sha.hexdigest() != rec["kernel_source_sha256"]:
         return None
     if rec.get("chunk_steps") != chunk:
         return None
