@@ -383,13 +383,19 @@ __global__ __launch_bounds__(BS) void k_band(DeviceNet d, uint32_t n_steps, uint
   // dt)), one byte per neuron: one Philox4x32-10 block per quad and step,
   // each word turned into a count by its population's inverse-CDF table.
   auto draw = [&](uint64_t t) -> uint32_t {
-    if (!(dcode >> 12)) return 0u;   // no real neuron in the quad
-    const Philox4 x = philox4x32_10(lq, uint32_t(t), uint32_t(t >> 32), kStreamThalamic,
-                                    uint32_t(seed), uint32_t(seed >> 32));
+    // The key, the counter word and the population codes pass through opaque
+    // copies at every draw, so that the round keys, the first round's product
+    // and the table addresses are formed here instead of being hoisted out of
+    // the step loop (about thirty registers held across the loop, spilled to
+    // scratch in the 1,024-thread variant).
+    uint32_t k0 = uint32_t(seed), k1 = uint32_t(seed >> 32), c0 = lq, dc = dcode;
+    asm volatile("" : "+v"(k0), "+v"(k1), "+v"(c0), "+v"(dc));
+    if (!(dc >> 12)) return 0u;   // no real neuron in the quad
+    const Philox4 x = philox4x32_10(c0, uint32_t(t), uint32_t(t >> 32), kStreamThalamic, k0, k1);
     uint32_t tp = 0;
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
-      const uint32_t pm = (dcode >> (3 * m)) & 7u;
+      const uint32_t pm = (dc >> (3 * m)) & 7u;
       const uint4 *tb = reinterpret_cast<const uint4 *>(s_thr + pm * TS);
       const uint4 lo = tb[0], hi = tb[1];
       const uint32_t len = s_tlen[pm];
@@ -405,7 +411,7 @@ __global__ __launch_bounds__(BS) void k_band(DeviceNet d, uint32_t n_steps, uint
         const uint32_t *tab = s_thr + pm * TS;
         while (c < len && u >= tab[c]) ++c;
       }
-      tp |= (((dcode >> (12 + m)) & 1u) ? c : 0u) << (8 * m);
+      tp |= (((dc >> (12 + m)) & 1u) ? c : 0u) << (8 * m);
     }
     return tp;
   };
@@ -513,7 +519,9 @@ __global__ __launch_bounds__(BS) void k_band(DeviceNet d, uint32_t n_steps, uint
             else
               ctl_v->overflow = 1;
           }
-          c_ev += OD[m];
+          uint32_t od = OD[m];   // opaque: keeps the 64-bit widening out of the loop
+          asm volatile("" : "+v"(od));
+          c_ev += od;
           ++p;
         }
       }
