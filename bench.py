@@ -163,6 +163,8 @@ def roofline(P, leg, workload):
     out = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
            "frac": achieved / HBM_PEAK_GBS,
            "traffic": (rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]) if rec else None,
+           "traffic_kind": "L2-to-fabric bytes per launch (FETCH_SIZE + WRITE_SIZE, scaled by a 1 GiB "
+                           "copy; Infinity Cache hits are included, the counters cannot separate them)",
            "kernel": kernel, "avg_launch_ms": avg_launch_ms,
            "bytes_per_launch": leg["bytes"] / leg["launches"]}
     if rec and "cache" in rec:

@@ -104,11 +104,23 @@ __device__ __forceinline__ void decode(uint64_t rec8, uint32_t rec4, uint32_t rb
 // Delivery of one batch of segments, one per lane of the wave: lane l holds
 // the segment (base, capacity) of the wave's sender l and its row base rb
 // (step of the spike, plus the band's first delay for compressed records,
-// whose delays are stored relative to it).  With every capacity at most
-// G <= 64 (a power of two) the senders are packed 64 / G to a load, G lanes
-// each; otherwise every sender is cut into 64-record pieces and each piece
-// takes a whole load.  UR loads are in flight per lane.
-template <bool COMP, int UR, int H>
+// whose delays are stored relative to it).  Three ways to cut the batch into
+// loads of 64 lanes:
+//  * grouped: with every capacity at most G <= 64 (a power of two, the
+//    band's largest capacity rounded up) the senders are packed 64 / G to a
+//    load, G lanes each;
+//  * pieces: every sender is cut into 64-record pieces, one load each;
+//  * packed: the segments are laid back to back and each load takes 64
+//    consecutive slots; slot k belongs to the last lane whose exclusive
+//    prefix of capacities is <= k (a binary search over the lanes).
+// Capacities of one band differ by up to two orders of magnitude between
+// populations, so the first two can leave most lanes empty; the packed walk
+// has the fewest loads but its search lengthens each load's address.  PACK
+// selects the packed walk for every batch; it is set only where that was
+// measured to pay (the 512-thread variant with 16 ring rows, whose slow bands
+// otherwise take several rounds of loads; elsewhere the other two fit one
+// round and are faster).  UR loads are in flight per lane.
+template <bool COMP, int UR, int H, bool PACK>
 struct BandWalk {
   uint64_t rec[COMP ? 1 : UR];
   uint32_t r4[COMP ? UR : 1];
@@ -116,8 +128,9 @@ struct BandWalk {
   uint64_t base_l;
   uint32_t cap_l, rb_l;
   uint32_t G;        // lanes per sender (grouped), or 64 with pieces
-  bool grouped;
-  uint32_t p_l;      // pieces mode: number of the lane's first piece
+  uint32_t mode;     // 0 grouped, 1 pieces, 2 packed (wave-uniform)
+  uint32_t p_l;      // pieces: the lane's first piece; packed: its first slot
+  uint32_t total;    // packed: slots of the batch
   uint32_t nu;       // units (loads of 64 lanes) of the batch, wave-uniform
   uint32_t u0;       // next unit
   uint32_t nv;       // slots filled by the last load()
@@ -128,13 +141,20 @@ struct BandWalk {
     cap_l = cap;
     rb_l = rb;
     u0 = 0;
-    grouped = gmax <= 64u;
-    if (grouped) {
+    total = 0;
+    if (PACK) {
+      mode = 2;
+      G = 64;
+      p_l = wave_prefix(cap, total);
+      nu = (total + 63u) >> 6;
+    } else if (gmax <= 64u) {
+      mode = 0;
       G = gmax;
       const uint32_t per = 64u / G;
       nu = (nsend + per - 1u) / per;
       p_l = 0;
     } else {
+      mode = 1;
       G = 64;
       p_l = wave_prefix((cap + 63u) >> 6, nu);
     }
@@ -150,29 +170,49 @@ struct BandWalk {
       rbv[u] = 0;
       if (U >= nu) continue;   // wave-uniform
       uint64_t addr;
-      uint32_t cap, off;
-      if (grouped) {
+      bool ok;
+      if (!PACK && mode == 0) {
         const uint32_t per = 64u / G;
         const uint32_t k = U * per + lane / G;   // sender (lane of the batch)
-        off = lane & (G - 1u);
+        const uint32_t off = lane & (G - 1u);
         const uint32_t blo = __shfl(uint32_t(base_l), int(k & 63u));
         const uint32_t bhi = __shfl(uint32_t(base_l >> 32), int(k & 63u));
-        cap = __shfl(cap_l, int(k & 63u));
+        uint32_t cap = __shfl(cap_l, int(k & 63u));
         rbv[u] = __shfl(rb_l, int(k & 63u));
         cap = k < 64u ? cap : 0u;
         addr = join64(bhi, blo) + off;
-      } else {
+        ok = off < cap;
+      } else if (!PACK) {
         // The piece's sender is the last lane whose first piece is <= U
         // (lanes past the last sender have p_l = nu > U).
         const uint32_t s = uint32_t(__popcll(__ballot(int(p_l <= U)))) - 1u;
         const uint32_t k = U - __builtin_amdgcn_readlane(p_l, s);
-        cap = __builtin_amdgcn_readlane(cap_l, s);
+        const uint32_t cap = __builtin_amdgcn_readlane(cap_l, s);
         rbv[u] = __builtin_amdgcn_readlane(rb_l, s);
-        off = 64u * k + lane;
+        const uint32_t off = 64u * k + lane;
         addr = join64(uint32_t(__builtin_amdgcn_readlane(uint32_t(base_l >> 32), s)),
                       uint32_t(__builtin_amdgcn_readlane(uint32_t(base_l), s))) + off;
+        ok = off < cap;
+      } else {
+        // Largest lane s with p_s <= slot: a slot below the total lies in a
+        // segment of positive capacity, so s is a real sender and the slot's
+        // offset in it is below its capacity.
+        const uint32_t slot = 64u * U + lane;
+        uint32_t s = 0, ps = 0;
+#pragma unroll
+        for (uint32_t step = 32; step; step >>= 1) {
+          const uint32_t c = s + step;
+          const uint32_t pc = __shfl(p_l, int(c));
+          const bool le = pc <= slot;
+          s = le ? c : s;
+          ps = le ? pc : ps;
+        }
+        const uint32_t blo = __shfl(uint32_t(base_l), int(s));
+        const uint32_t bhi = __shfl(uint32_t(base_l >> 32), int(s));
+        rbv[u] = __shfl(rb_l, int(s));
+        addr = join64(bhi, blo) + (slot - ps);
+        ok = slot < total;
       }
-      const bool ok = off < cap;
       if (COMP) {
         if (ok) r4[u] = __builtin_nontemporal_load(d.rec4 + addr);
       } else {
@@ -233,6 +273,7 @@ __global__ __launch_bounds__(BS) void k_band(DeviceNet d, uint32_t n_steps, uint
   constexpr uint32_t RC = 640;                 // raster staging entries
   constexpr uint32_t SB = 64 * NW;             // senders resolved per round
   constexpr int UR = BS >= 1024 ? 4 : 8;       // loads in flight per lane (register budget)
+  constexpr bool PACK = BS == 512;             // packed walk (the variant of the widest bands)
   static_assert(Q0 >= 128, "waves 0 and 1 own no quad");
   static_assert(NSLOT > LOMAX, "the history must reach the last slow band");
   static_assert((H & (H - 1)) == 0 && H >= 8 && H <= 64, "ring rows: a power of two in [8, 64]");
@@ -305,6 +346,7 @@ __global__ __launch_bounds__(BS) void k_band(DeviceNet d, uint32_t n_steps, uint
     s_tlen[tid] = m.y;
   }
   __syncthreads();
+
   if (tid < NB) {   // group width of each band: the next power of two of its largest capacity
     uint32_t mx = 0;
     for (int c = 0; c < 8; ++c) mx = max(mx, s_cn[c] ? s_ccap[tid * 8 + c] : 0u);
@@ -584,7 +626,7 @@ __global__ __launch_bounds__(BS) void k_band(DeviceNet d, uint32_t n_steps, uint
           base = s_cbase[j * 8 + ci] + uint64_t(gid - s_cf[ci]) * cap;
           rb = uint32_t(s) + (COMP ? band_lo(j, H) : 0u);
         }
-        BandWalk<COMP, UR, H> bw;
+        BandWalk<COMP, UR, H, PACK> bw;
         bw.begin(base, cap, rb, n_l, gs);
         while (bw.more()) {
           bw.load(d);
@@ -666,10 +708,10 @@ __global__ __launch_bounds__(BS) void k_band(DeviceNet d, uint32_t n_steps, uint
     // (c3) band 0 of step t-1's senders; their ids go to the history.
     const uint32_t n0 = __builtin_amdgcn_readfirstlane(s_n[0]);
     const uint32_t n_prev = n0 + __builtin_amdgcn_readfirstlane(s_n[1]);
+    const uint32_t g0 = s_gmax[0];
     const uint64_t tsrc = t - 1;
     const uint32_t hslot = uint32_t(tsrc % NSLOT);
     if (tid == 0) s_hn[hslot] = n_prev;
-    const uint32_t g0 = s_gmax[0];
     for (uint32_t j0 = 0; j0 < n_prev; j0 += SB) {
       const uint32_t nb = min(SB, n_prev - j0);
       const uint32_t n_l = nb > wave ? (nb - wave + NW - 1u) / NW : 0u;
@@ -690,7 +732,7 @@ __global__ __launch_bounds__(BS) void k_band(DeviceNet d, uint32_t n_steps, uint
         cap = gid - s_cf[ci] < s_cn[ci] ? s_ccap[ci] : 0u;
         base = s_cbase[ci] + uint64_t(gid - s_cf[ci]) * cap;
       }
-      BandWalk<COMP, UR, H> bw;
+      BandWalk<COMP, UR, H, PACK> bw;
       bw.begin(base, cap, uint32_t(tsrc) + (COMP ? 1u : 0u), n_l, g0);
       while (bw.more()) {
         bw.load(d);
@@ -725,7 +767,7 @@ __global__ __launch_bounds__(BS) void k_band(DeviceNet d, uint32_t n_steps, uint
             cap = gid - s_cf[ci] < s_cn[ci] ? s_ccap[j * 8 + ci] : 0u;
             base = s_cbase[j * 8 + ci] + uint64_t(gid - s_cf[ci]) * cap;
           }
-          BandWalk<COMP, UR, H> bw;
+          BandWalk<COMP, UR, H, PACK> bw;
           bw.begin(base, cap, uint32_t(s) + (COMP ? lo_j : 0u), n_l, gj);
           while (bw.more()) {
             bw.load(d);
