@@ -66,17 +66,21 @@ enum snn_engine {
   SNN_ENGINE_STEPWISE = 1,    /* two kernels per step (update, then transfer)    */
   SNN_ENGINE_PERSISTENT = 2,  /* one cooperative kernel per chunk of steps, one
                                  grid-wide barrier per step, ring in HBM          */
-  SNN_ENGINE_LDS = 3,         /* persistent, each block owning 256 or 512 neurons
-                                 and their 64 ring rows in LDS; synapses stored
-                                 per (sender, destination block); needs the whole
-                                 network to fit the co-resident blocks            */
+  SNN_ENGINE_LDS = 3,         /* persistent, each block owning up to 320 or 512
+                                 neurons and their 64 ring rows in LDS; synapses
+                                 stored per (sender, destination block).  The
+                                 automatic choice when the whole network fits
+                                 the co-resident blocks; requested explicitly,
+                                 instances beyond that run as several launches
+                                 per chunk (groups of whole instances)            */
   SNN_ENGINE_BAND = 4         /* persistent, each block owning up to 3,584 neurons
                                  and H = 64, 16 or 8 rows of their ring in LDS:
                                  horizon-based transfer (Sec. 3.4, lst:horizon2)
                                  with synapses stored per (sender, destination
-                                 block, delay band); the one-step delays are
-                                 delivered first, the other bands while blocks
-                                 wait for each other's spikes                     */
+                                 block, delay band); the slow bands are
+                                 delivered while the spikes of the last step
+                                 propagate between blocks, the one-step delays
+                                 once they have arrived                           */
 };
 
 /* One microcircuit instance.  Defaults (snn_instance_default) are the

@@ -581,10 +581,10 @@ __global__ __launch_bounds__(BS) void k_band(DeviceNet d, uint32_t n_steps, uint
         st_ag(flags + size_t(ep % kSlots) * GT + blk, f);
       }
       if (!direct) rn += cnt;
-      if (owner) Tp = draw(t);                 // T_t, used when step t completes
     }
 
     if (it == 0) {   // nothing to deliver yet
+      if (decide && owner) Tp = draw(t);     // T_t, used when step t completes
       __syncthreads();
       continue;
     }
@@ -636,7 +636,7 @@ __global__ __launch_bounds__(BS) void k_band(DeviceNet d, uint32_t n_steps, uint
     }
 
     // (c2) waves 0 and 1 wait for step t-1's flags of their windows and
-    // stage their senders.
+    // stage their senders; the quad owners draw T_t meanwhile.
     if (poller) {
       uint32_t spins = 0;
       bool ok = true;
@@ -698,6 +698,9 @@ __global__ __launch_bounds__(BS) void k_band(DeviceNet d, uint32_t n_steps, uint
         s_n[h] = all_s;
         s_flag[h] = ok ? 1u : 0u;
       }
+    } else if (decide && owner) {
+      // The other waves draw T_t meanwhile (used when step t completes).
+      Tp = draw(t);
     }
     __syncthreads();
 
