@@ -90,7 +90,8 @@ int orc_build(const orc_config *c, orc_net **out) {
     orc_error("bg_rate_hz, psp_ext_mv must be >= 0 and g <= 0");
     return ORC_E_INVAL;
   }
-  if (c->weight_mode != ORC_W_PLAIN && c->weight_mode != ORC_W_COMPRESSED) {
+  if (c->weight_mode != ORC_W_PLAIN && c->weight_mode != ORC_W_COMPRESSED &&
+      c->weight_mode != ORC_W_DEV8) {
     orc_error("unknown weight mode %d", c->weight_mode);
     return ORC_E_INVAL;
   }
@@ -167,6 +168,8 @@ int orc_build(const orc_config *c, orc_net **out) {
       if (b == 0 && a == 2) psp = 2.0 * psp_e;
       double mu_w = psp * n->k.w_f;
       double sd_w = 0.1 * fabs(mu_w);
+      n->mu_w[b][a] = mu_w;
+      n->sd_w[b][a] = sd_w;
       double mu_d = orc_is_exc(a) ? 15.0 : 7.5;
       double sd_d = orc_is_exc(a) ? 7.5 : 3.75;
       uint32_t pair = (uint32_t)(8 * b + a);
@@ -213,8 +216,10 @@ int orc_build(const orc_config *c, orc_net **out) {
   free(cur);
   free(g_pre); free(g_post); free(g_d); free(g_w);
 
-  /* Fixed-point weights: 2^-8 pA (plain), or int16 in 2^-5 pA scaled to the
-   * same 2^-8 pA accumulator (compressed, Sec. 5.3's 16-bit weights). */
+  /* Fixed-point weights: 2^-8 pA (plain), int16 in 2^-5 pA scaled to the
+   * same 2^-8 pA accumulator (compressed, Sec. 5.3's 16-bit weights), or the
+   * pair's mean plus an 8-bit deviation (dev8, Sec. 5.3's deviations from the
+   * mean; below). */
   for (uint64_t e = 0; e < S; ++e) {
     double w = n->w[e];
     if (c->weight_mode == ORC_W_PLAIN) {
@@ -225,7 +230,7 @@ int orc_build(const orc_config *c, orc_net **out) {
         goto fail;
       }
       n->w_q[e] = (int32_t)q;
-    } else {
+    } else if (c->weight_mode == ORC_W_COMPRESSED) {
       double q = nearbyint(w * 32.0);
       if (!(q >= -32768.0 && q <= 32767.0)) {
         orc_error("weight %g pA does not fit the 16-bit encoding", w);
@@ -233,6 +238,18 @@ int orc_build(const orc_config *c, orc_net **out) {
         goto fail;
       }
       n->w_q[e] = 8 * (int32_t)q;
+    }
+  }
+  if (c->weight_mode == ORC_W_DEV8) {
+    /* The pair of a synapse: the populations of its receiver and sender. */
+    for (uint32_t i = 0; i < n->N; ++i) {
+      int a = n->pop_of[i];
+      for (uint64_t e = n->row_ptr[i]; e < n->row_ptr[i + 1]; ++e) {
+        int b = n->pop_of[n->post[e]];
+        int32_t mq, sq, dev;
+        orc_dev8_params(n->mu_w[b][a], n->sd_w[b][a], &mq, &sq);
+        n->w_q[e] = orc_dev8_encode(n->w[e], mq, sq, &dev);
+      }
     }
   }
 
@@ -320,6 +337,22 @@ const uint32_t *orc_net_post(const orc_net *n) { return n->post; }
 const uint8_t *orc_net_delay(const orc_net *n) { return n->delay; }
 const double *orc_net_weight(const orc_net *n) { return n->w; }
 const int32_t *orc_net_weight_q(const orc_net *n) { return n->w_q; }
+void orc_net_dev8_pair(const orc_net *n, int target, int source, int32_t *mq, int32_t *sq) {
+  orc_dev8_params(n->mu_w[target][source], n->sd_w[target][source], mq, sq);
+}
+
+void orc_dev8_params(double mu, double sd, int32_t *mq, int32_t *sq) {
+  double s = nearbyint(5.0 * sd * 256.0 / 127.0);
+  *mq = (int32_t)nearbyint(mu * 256.0);
+  *sq = s < 1.0 ? 1 : (int32_t)s;
+}
+
+int32_t orc_dev8_encode(double w, int32_t mq, int32_t sq, int32_t *dev) {
+  double r = nearbyint((w * 256.0 - (double)mq) / (double)sq);
+  int32_t d = r < -127.0 ? -127 : (r > 127.0 ? 127 : (int32_t)r);
+  *dev = d;
+  return mq + d * sq;
+}
 const float *orc_net_u0(const orc_net *n) { return n->u0; }
 const double *orc_net_u0_f64(const orc_net *n) { return n->u0d; }
 int orc_net_poisson(const orc_net *n, int p, const uint32_t **thr, int *len) {

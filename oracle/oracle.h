@@ -54,7 +54,10 @@ enum {
 /* Weight encoding used by ORC_ARITH_INT32. */
 enum {
   ORC_W_PLAIN = 0,      /* w_q = round(w * 2^8)                  (2^-8 pA)  */
-  ORC_W_COMPRESSED = 1  /* w_q = 8 * round(w * 2^5), int16 range (2^-5 pA) */
+  ORC_W_COMPRESSED = 1, /* w_q = 8 * round(w * 2^5), int16 range (2^-5 pA) */
+  ORC_W_DEV8 = 2        /* w_q = mq + dev * sq: the pair's mean mq and an
+                           8-bit deviation dev in steps sq (Sec. 5.3's
+                           deviations from the mean; orc_dev8_params)      */
 };
 
 typedef struct {
@@ -70,7 +73,7 @@ typedef struct {
   double bg_rate_hz;        /* thalamic rate v_th (default 8 Hz)              */
   double psp_ext_mv;        /* thalamic PSP amplitude omega_ext (0.15 mV)     */
   int bg_const_T;           /* -1: Poisson drive; >= 0: T_t fixed to this     */
-  int weight_mode;          /* ORC_W_PLAIN or ORC_W_COMPRESSED                */
+  int weight_mode;          /* ORC_W_PLAIN, ORC_W_COMPRESSED or ORC_W_DEV8    */
   const double *conn;       /* NULL, or 64 probabilities [target][source]     */
 } orc_config;
 
@@ -87,6 +90,17 @@ typedef struct {
 } orc_consts;
 
 int orc_constants(const orc_config *c, orc_consts *out);
+
+/* ORC_W_DEV8 (Sec. 5.3: the synaptic weights are drawn from Gaussians with
+ * known means, so their deviations from the mean need fewer bits).  For a
+ * population pair of mean weight mu and standard deviation sd (pA):
+ *   mq  = round(mu * 2^8)                         (2^-8 pA, round half even)
+ *   sq  = max(1, round(5 sd * 2^8 / 127))         (the step: 5 sd over 127)
+ *   dev = clamp(round((w * 2^8 - mq) / sq), -127, 127)
+ *   w_q = mq + dev * sq
+ * so |w_q - w * 2^8| <= sq / 2 unless |w - mu| exceeds about 5 sd. */
+void orc_dev8_params(double mu, double sd, int32_t *mq, int32_t *sq);
+int32_t orc_dev8_encode(double w, int32_t mq, int32_t sq, int32_t *dev);
 
 /* Philox4x32-10 (Salmon et al., SC'11): out = bijection(ctr) under key. */
 void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
@@ -116,6 +130,8 @@ const uint32_t *orc_net_post(const orc_net *n);
 const uint8_t *orc_net_delay(const orc_net *n);
 const double *orc_net_weight(const orc_net *n);
 const int32_t *orc_net_weight_q(const orc_net *n);
+/* Mean and step (2^-8 pA) of pair [target][source] under ORC_W_DEV8. */
+void orc_net_dev8_pair(const orc_net *n, int target, int source, int32_t *mq, int32_t *sq);
 const float *orc_net_u0(const orc_net *n);            /* initial U, mV rel. E_L */
 const double *orc_net_u0_f64(const orc_net *n);
 /* Poisson table of population p. */

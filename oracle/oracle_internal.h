@@ -34,6 +34,8 @@ struct orc_net {
   uint32_t n_pop[8];
   uint32_t off[9];
   uint64_t pair_n[8][8];      /* [target][source]                            */
+  double mu_w[8][8];          /* mean weight of each pair, pA [target][source] */
+  double sd_w[8][8];          /* its standard deviation, pA                    */
   uint64_t S;
   uint64_t *row_ptr;          /* N + 1                                       */
   uint32_t *post;

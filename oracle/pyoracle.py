@@ -18,6 +18,7 @@ ARITH_INT32 = 0
 ARITH_F64 = 1
 W_PLAIN = 0
 W_COMPRESSED = 1
+W_DEV8 = 2
 
 
 class _Cfg(C.Structure):
@@ -124,6 +125,12 @@ def lib():
         L.orc_single_neuron_f64.argtypes = [C.POINTER(_Consts), C.POINTER(C.c_double), C.c_uint64,
                                             C.POINTER(C.c_double), C.POINTER(C.c_double),
                                             C.POINTER(C.c_int32)]
+        L.orc_dev8_params.argtypes = [C.c_double, C.c_double, C.POINTER(C.c_int32),
+                                      C.POINTER(C.c_int32)]
+        L.orc_dev8_encode.argtypes = [C.c_double, C.c_int32, C.c_int32, C.POINTER(C.c_int32)]
+        L.orc_dev8_encode.restype = C.c_int32
+        L.orc_net_dev8_pair.argtypes = [vp, C.c_int, C.c_int, C.POINTER(C.c_int32),
+                                        C.POINTER(C.c_int32)]
         L.orc_last_error.restype = C.c_char_p
     return _lib
 
@@ -200,6 +207,20 @@ def poisson_table(lam, cap=64):
     return np.array(thr[: n.value], dtype=np.uint64)
 
 
+def dev8_params(mu, sd):
+    """(mq, sq) of a pair of mean mu and standard deviation sd (pA) under W_DEV8."""
+    a, b = C.c_int32(), C.c_int32()
+    lib().orc_dev8_params(float(mu), float(sd), C.byref(a), C.byref(b))
+    return a.value, b.value
+
+
+def dev8_encode(w, mq, sq):
+    """(w_q, dev) of a weight w (pA) under W_DEV8."""
+    d = C.c_int32()
+    wq = lib().orc_dev8_encode(float(w), int(mq), int(sq), C.byref(d))
+    return wq, d.value
+
+
 def pair_counts(cfg: Optional[Config] = None):
     """Synapse counts [target][source] without sampling the network."""
     cfg = cfg or Config()
@@ -256,6 +277,17 @@ class Net:
                 _arr(L.orc_net_delay(self.h), S, np.uint8),
                 _arr(L.orc_net_weight(self.h), S, np.float64),
                 _arr(L.orc_net_weight_q(self.h), S, np.int32))
+
+    def dev8_pairs(self):
+        """Mean and step (2^-8 pA) of every pair [target][source] under W_DEV8."""
+        mq = np.zeros((8, 8), dtype=np.int64)
+        sq = np.zeros((8, 8), dtype=np.int64)
+        a, b = C.c_int32(), C.c_int32()
+        for t in range(8):
+            for s in range(8):
+                lib().orc_net_dev8_pair(self.h, t, s, C.byref(a), C.byref(b))
+                mq[t, s], sq[t, s] = a.value, b.value
+        return mq, sq
 
     def u0(self):
         return _arr(lib().orc_net_u0(self.h), self.N, np.float32)

@@ -143,6 +143,24 @@ def test_pull_brute_force_reproduces_push(oracle, tiny):
     np.testing.assert_array_equal(st["R"], R)
 
 
+def test_pull_brute_force_reproduces_push_dev8(oracle):
+    """The same dense lst:pull check on the dev8 weights (pair mean plus an
+    8-bit deviation): the push delivery of the oracle does not depend on how
+    the weights were quantised."""
+    net = oracle.Net(oracle.Config(scale=0.01, seed=4, weight_mode=oracle.W_DEV8))
+    sim = oracle.Sim(net, record_inputs=True).run(400)
+    T_rec, w_rec = sim.recorded_inputs()
+    raster, inputs, U, I, R = pull_simulation(net, T_rec, 400)
+    steps, ids = sim.raster()
+    assert len(steps) > 1000
+    np.testing.assert_array_equal(inputs, w_rec)
+    np.testing.assert_array_equal(raster[:, 0], steps)
+    np.testing.assert_array_equal(raster[:, 1], ids)
+    st = sim.state()
+    np.testing.assert_array_equal(st["U"], U)
+    np.testing.assert_array_equal(st["I"], I)
+
+
 def test_delivered_events_and_charge_conservation(oracle, tiny):
     """Every spike activates each outgoing synapse exactly once: delivered
     events = sum of sender out-degrees, and the charge injected equals what

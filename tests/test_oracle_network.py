@@ -190,6 +190,57 @@ def test_weight_quantisation(oracle):
     assert np.abs(wq2 // 8).max() <= 32767
 
 
+def test_dev8_weights_are_pair_mean_plus_small_deviation(oracle):
+    """Sec. 5.3's deviations from the mean: every dev8 weight is its pair's
+    mean plus an integer number of steps (|steps| <= 127), within half a step
+    of the sampled weight unless the deviation exceeds the clip range; the
+    pair is (receiver population, sender population), so a swapped index, a
+    lost doubling of L4e -> L2/3e or a wrong inhibitory sign breaks the
+    bound by thousands of steps."""
+    cfg = oracle.Config(scale=0.05, weight_mode=oracle.W_DEV8, g=-4.5)
+    net = oracle.Net(cfg)
+    rp, post, _, w, wq = net.csr()
+    off = net.pop_offsets()
+    pop = np.searchsorted(off, np.arange(net.N), side="right") - 1
+    pre = np.repeat(np.arange(net.N), np.diff(rp).astype(np.int64))
+    tgt, src = pop[post], pop[pre]
+    mq, sq = net.dev8_pairs()
+    m, q = mq[tgt, src], sq[tgt, src]
+    steps = (wq - m) // q
+    assert np.all((wq - m) % q == 0)
+    assert np.all(np.abs(steps) <= 127)
+    err = np.abs(wq - w * 256.0)
+    inside = np.abs(w * 256.0 - m) <= 126.5 * q
+    assert np.all(err[inside] <= q[inside] / 2 + 1e-6)
+    # The clip range is 5 standard deviations: its two-sided normal tail is
+    # 5.7e-7, so at most a handful of the ~7e5 synapses lie outside it.
+    assert (~inside).sum() <= 5
+    # Means and steps from the paper's weights: 0.15 mV times w_f, twice for
+    # L4e -> L2/3e, g times for inhibitory senders; sd 10 % of the mean.
+    k = oracle.constants(cfg)
+    for b, a in [(0, 0), (0, 2), (3, 1), (6, 7), (4, 2)]:
+        mu = 0.15 * k["w_f"] * (2.0 if (b, a) == (0, 2) else (1.0 if a % 2 == 0 else cfg.g))
+        assert mq[b, a] == round(mu * 256.0)
+        assert abs(sq[b, a] - 5.0 * 0.1 * abs(mu) * 256.0 / 127.0) <= 0.5
+    # Per pair, the quantised weights keep the sampled mean and spread.
+    for b, a in [(0, 2), (2, 0), (4, 5)]:
+        sel = (tgt == b) & (src == a)
+        x, y = wq[sel] / 256.0, w[sel]
+        assert abs(x.mean() - y.mean()) <= sq[b, a] / 256.0 / np.sqrt(12 * sel.sum()) * 6 + 1e-9
+        assert x.std() == pytest.approx(y.std(), rel=0.01)
+
+
+def test_dev8_encode_edges(oracle):
+    mq, sq = oracle.dev8_params(100.0, 10.0)
+    assert (mq, sq) == (25600, round(50.0 * 256.0 / 127.0))
+    assert oracle.dev8_encode(100.0, mq, sq) == (mq, 0)
+    assert oracle.dev8_encode(100.0 + 1e6, mq, sq) == (mq + 127 * sq, 127)
+    assert oracle.dev8_encode(100.0 - 1e6, mq, sq) == (mq - 127 * sq, -127)
+    wq, d = oracle.dev8_encode(100.0 + 3.5 * sq / 256.0, mq, sq)   # a tie rounds to even
+    assert d == 4 and wq == mq + 4 * sq
+    assert oracle.dev8_params(0.0, 0.0) == (0, 1)
+
+
 def test_seed_changes_network(oracle):
     a = oracle.Net(oracle.Config(scale=0.01, seed=1)).csr()
     b = oracle.Net(oracle.Config(scale=0.01, seed=2)).csr()
