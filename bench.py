@@ -8,8 +8,9 @@ read-back of the timed window's spike rasters, bracketed by
 torch.cuda.synchronize(); networks are built and uploaded before it.
 
 Workloads (--workload selects the headline one):
-  full   the full-scale circuit, 77,169 neurons, ~3e8 synapses; plain and
-         compressed legs; defaults 1 warm-up + 10 timed seconds (the paper's
+  full   the full-scale circuit, 77,169 neurons, ~3e8 synapses; plain,
+         compressed and dev8 (pair mean plus 8-bit deviation, 3-byte
+         synapses) legs; defaults 1 warm-up + 10 timed seconds (the paper's
          10 s runs).  The default.
   batch  64 independent instances of uneven scale (5-20 %), g and background
          rate, compressed synapses; 2 timed seconds.
@@ -37,7 +38,7 @@ STEPS_PER_BIO_SECOND = 10000
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, 8 TB/s
 
 WORKLOADS = {
-    "full": {"legs": ["plain", "compressed"], "steps": 10,
+    "full": {"legs": ["plain", "compressed", "dev8"], "steps": 10,
              "name": "full-scale PD microcircuit, 77,169 neurons, {syn} synapses, dt 0.1 ms"},
     "batch": {"legs": ["compressed"], "steps": 2,
               "name": "64 independent PD instances, scale U[5%,20%], g U[-6,-3], background "
@@ -105,7 +106,7 @@ def run_leg(P, instances, fmt, engine, chunk, warm_bio_s, timed_bio_s, log, tune
     assert spikes == n_raster, (spikes, n_raster)
     n = sum(b["n_neurons"] for b in s1)
     windowed = info["engine"] in (P.ENGINE_LDS, P.ENGINE_BAND)
-    rec = 8.0 if fmt == "plain" else (4.0 if windowed else 5.0)
+    rec = {"plain": 8.0, "dev8": 3.0}.get(fmt, 4.0 if windowed else 5.0)
     ring_b, syn_b = algorithmic_bytes(n, spikes, events, rec)
     total_bytes = ring_b * n_steps + syn_b
     chunked = info["engine"] in (P.ENGINE_PERSISTENT, P.ENGINE_LDS, P.ENGINE_BAND)
@@ -222,7 +223,7 @@ def leg_summary(P, leg, bio, workload):
             "us_per_sim_step_gpu": 1000.0 * leg["gpu_ms"] / leg["n_steps"],
             "spikes_per_step": leg["spikes"] / leg["n_steps"],
             "events_per_step": leg["events"] / leg["n_steps"],
-            "syn_format": "plain8" if leg["fmt"] == "plain" else "compressed",
+            "syn_format": {"plain": "plain8"}.get(leg["fmt"], leg["fmt"]),
             "record_bytes": leg["rec_bytes"], "build_s": leg["build_s"],
             "device_bytes": info["device_bytes"], "engine": info["engine"],
             "block": info["block_size"], "grid": info["grid_blocks"],
@@ -234,7 +235,7 @@ def run_workload(P, workloads, name, args, log, bio_steps=None):
     wl = WORKLOADS[name]
     bio = bio_steps if bio_steps is not None else wl["steps"]
     instances = workloads.WORKLOADS[name]()
-    legs = [f for f in wl["legs"] if not (f == "compressed" and args.no_compressed)
+    legs = [f for f in wl["legs"] if not (f in ("compressed", "dev8") and args.no_compressed)
             and not (f == "plain" and args.no_plain)] or wl["legs"][:1]
     return bio, instances, [run_leg(P, instances, f, args.engine, args.chunk, args.warmup, bio, log,
                                     args.tune_steps, args.tune_cache) for f in legs]
@@ -249,7 +250,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1, help="untimed seconds of biological time")
     ap.add_argument("--engine", default="auto", choices=["auto", "stepwise", "persistent", "lds", "band"])
     ap.add_argument("--chunk", type=int, default=10000, help="simulation steps per launch (chunk)")
-    ap.add_argument("--no-compressed", action="store_true", help="skip the compressed-synapse legs")
+    ap.add_argument("--no-compressed", action="store_true",
+                    help="skip the compressed and dev8 synapse legs")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain-synapse legs")
     ap.add_argument("--no-extra", action="store_true",
                     help="with the full workload: skip the batch and x4 workloads")
@@ -305,7 +307,7 @@ def main():
         "config": {"workload": wl["name"].format(syn=info["n_synapses_total"],
                                                  neurons=first["n_neurons"]),
                    "steps_per_bench_step": STEPS_PER_BIO_SECOND,
-                   "syn_format": "plain8" if first["fmt"] == "plain" else "compressed",
+                   "syn_format": {"plain": "plain8"}.get(first["fmt"], first["fmt"]),
                    "instances": len(instances), "engine": info["engine"],
                    "block": info["block_size"], "grid": info["grid_blocks"],
                    "window_neurons": info["window_neurons"], "ring_rows": info["ring_rows"],

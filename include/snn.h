@@ -55,8 +55,17 @@ enum snn_syn_format {
   SNN_SYN_PLAIN8 = 0,
   /* 5 bytes in three streams: uint16 target offset inside a 65,536-neuron
      target block, int16 weight in 2^-5 pA, uint8 delay; sorted by sender,
-     then target block (the 16-bit weights of Sec. 5.3). */
-  SNN_SYN_COMPRESSED5 = 1
+     then target block (the 16-bit weights of Sec. 5.3).  The LDS engines
+     pack the same weight, delay and window offset into one 4-byte record. */
+  SNN_SYN_COMPRESSED5 = 1,
+  /* 3 bytes in two streams, LDS engine only: a uint16 locator (bit 15: the
+     doubled L4e -> L2/3e pair; bits 9-14: delay; bits 0-8: target offset in
+     a window of at most 512 neurons) and an int8 deviation of the weight from
+     the mean of its population pair, in steps of 5 sd / 127 of that pair;
+     the weight is mean + deviation * step in 2^-8 pA, both rounded to that
+     unit (Sec. 5.3: the weights are drawn from Gaussians of known mean, so
+     their deviations from the mean need fewer bits). */
+  SNN_SYN_DEV8 = 2
 };
 
 /* Step-loop engines. */

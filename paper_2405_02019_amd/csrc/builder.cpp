@@ -102,7 +102,8 @@ int prepare_instance(const snn_instance_cfg &cfg, uint32_t syn_format, int &thre
     err = "need g <= 0, bg_rate_hz >= 0 and psp_ext_mv >= 0";
     return SNN_E_INVAL;
   }
-  if (syn_format != SNN_SYN_PLAIN8 && syn_format != SNN_SYN_COMPRESSED5) {
+  if (syn_format != SNN_SYN_PLAIN8 && syn_format != SNN_SYN_COMPRESSED5 &&
+      syn_format != SNN_SYN_DEV8) {
     err = "unknown synapse format";
     return SNN_E_INVAL;
   }
@@ -193,6 +194,14 @@ int prepare_instance(const snn_instance_cfg &cfg, uint32_t syn_format, int &thre
       pr.sd_d = exc ? 7.5 : 3.75;
       pairs.push_back(pr);
       S += c;
+      // Deviation format (Sec. 5.3: weights as deviations from the mean of
+      // their Gaussian): the mean of the pair and a step of 5 sd / 127, both
+      // in 2^-8 pA.  Pairs of one sender population share them, except the
+      // doubled L4e -> L2/3e pair.
+      const int di = int(2 * a + ((b == 0 && a == 2) ? 1 : 0));
+      const double st = std::nearbyint(5.0 * pr.sd_w * 256.0 / 127.0);
+      out.dev_mq[di] = int32_t(std::nearbyint(pr.mu_w * 256.0));
+      out.dev_sq[di] = st < 1.0 ? 1 : int32_t(st);
     }
   out.nsyn = S;
 
@@ -210,6 +219,11 @@ int sample_instance(const snn_instance_cfg &cfg, uint32_t syn_format, uint32_t w
   if (rc) return rc;
   const uint64_t S = out.nsyn;
   const bool comp = syn_format == SNN_SYN_COMPRESSED5;
+  const bool dev = syn_format == SNN_SYN_DEV8;
+  if (dev && (!pad || win_size > 512)) {
+    err = "the deviation format needs the LDS engine's layout (windows of at most 512 neurons)";
+    return SNN_E_INVAL;
+  }
   if (win_size == 0 || (comp && win_size > (1u << kTargetBlockBits))) {
     err = "target windows must hold 1 .. 65,536 neurons for 16-bit target offsets";
     return SNN_E_RANGE;
@@ -329,7 +343,12 @@ int sample_instance(const snn_instance_cfg &cfg, uint32_t syn_format, uint32_t w
   out.tgt16.clear();
   out.w16.clear();
   out.d8.clear();
-  if (pack4) {
+  out.rec2.clear();
+  out.dev8.clear();
+  if (dev) {
+    out.rec2.assign(R, 0);
+    out.dev8.assign(R, 0);
+  } else if (pack4) {
     out.rec4.assign(R, 0);
   } else if (comp) {
     out.tgt16.assign(R, 0);
@@ -365,7 +384,19 @@ int sample_instance(const snn_instance_cfg &cfg, uint32_t syn_format, uint32_t w
       const uint64_t seg = uint64_t(pre) * nwin + window(post);
       const uint64_t pos = c[seg]++;
       int32_t wq;
-      if (comp) {
+      if (dev) {
+        // mean + deviation * step, the deviation rounded half to even and
+        // clipped to 8 bits.
+        const uint32_t dbl = (pr.tgt == 0 && pr.src == 2) ? 1u : 0u;
+        const int di = int(2 * pr.src + dbl);
+        const int32_t mq = out.dev_mq[di], sq = out.dev_sq[di];
+        const double r = std::nearbyint((w * 256.0 - double(mq)) / double(sq));
+        const int32_t dv = r < -127.0 ? -127 : (r > 127.0 ? 127 : int32_t(r));
+        const uint32_t off = uint32_t((uint64_t(win_origin) + post) % win_size);
+        out.rec2[pos] = uint16_t((dbl << 15) | (d << 9) | off);
+        out.dev8[pos] = int8_t(dv);
+        wq = mq + dv * sq;
+      } else if (comp) {
         const double q = std::nearbyint(w * 32.0);
         if (!(q >= -32768.0 && q <= 32767.0)) {
           bad.store(2);
@@ -429,6 +460,10 @@ int sample_instance(const snn_instance_cfg &cfg, uint32_t syn_format, uint32_t w
 // the segment lengths (capacities) and the placement.
 int sample_instance_banded(const snn_instance_cfg &cfg, uint32_t syn_format, uint32_t win_size,
                            uint32_t band_h, int threads, HostInstance &out, std::string &err) {
+  if (syn_format == SNN_SYN_DEV8) {
+    err = "the deviation format is stored for the LDS engine only";
+    return SNN_E_INVAL;
+  }
   std::vector<Pair> pairs;
   uint32_t n_pop[8], tmax = 0;
   int rc = prepare_instance(cfg, syn_format, threads, out, pairs, n_pop, tmax, err);

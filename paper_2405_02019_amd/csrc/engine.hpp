@@ -73,6 +73,8 @@ struct DeviceNet {
   const uint64_t *seg_ptr = nullptr;
   const uint64_t *rec8 = nullptr;
   const uint32_t *rec4 = nullptr;   // LDS engine, compressed: w16 << 16 | delay << 10 | offset
+  const uint16_t *rec2 = nullptr;   // LDS engine, deviation format: doubled << 15 | delay << 9 | offset
+  const int8_t *dev8 = nullptr;     // and the weight's deviation (steps of InstDev::dev_sq)
   const uint16_t *tgt16 = nullptr;
   const int16_t *w16 = nullptr;
   const uint8_t *d8 = nullptr;

@@ -857,6 +857,11 @@ __device__ __forceinline__ uint32_t sender_gid(const uint32_t *llist, uint32_t n
   return w0 + ld_ag(llist + size_t(lslot) * ntot + w0 + kk);
 }
 
+// Record formats of the LDS engine: 8-byte plain records, 4-byte compressed
+// records (16-bit weight), and the deviation format's 2-byte locator plus
+// 8-bit deviation from the pair's mean (Sec. 5.3).
+constexpr int kFmtPlain = 0, kFmtComp = 1, kFmtDev = 2;
+
 // UR record slots per lane.  The wave's senders of a batch are held one per
 // lane (segment address and capacity); their segments are cut into 64-record
 // pieces, numbered sender by sender.  load() takes the next UR pieces, one per
@@ -864,21 +869,26 @@ __device__ __forceinline__ uint32_t sender_gid(const uint32_t *llist, uint32_t n
 // ballot), so a piece's address costs a few scalar operations and no branch.
 // apply() adds the loaded records into rows (t_src + delay).  Unused slots and
 // empty record slots (delay 0) add nothing.
-template <bool COMP, int UR>
+template <int FMT, int UR>
 struct SegmentWalk {
-  uint64_t rec[COMP ? 1 : UR];
-  uint32_t r4[COMP ? UR : 1];
+  uint64_t rec[FMT == kFmtPlain ? UR : 1];
+  uint32_t r4[FMT == kFmtComp ? UR : 1];
+  uint32_t r2[FMT == kFmtDev ? UR : 1];    // deviation format: locator
+  int32_t dv[FMT == kFmtDev ? UR : 1];     // and deviation
+  uint32_t pc[FMT == kFmtDev ? UR : 1];    // and the piece's sender population (wave-uniform)
   uint64_t base_l;   // lane l: segment of the wave's sender l
   uint32_t cap_l;
+  uint32_t cls_l;    // lane l: population of the wave's sender l
   uint32_t p_l;      // lane l: number of the sender's first piece
   uint32_t np;       // pieces of the batch (wave-uniform)
   uint32_t p0;       // next piece
   uint32_t nv;       // slots filled by the last load()
 
   // Lane l holds the segment of the wave's sender l (capacity 0 past the end).
-  __device__ __forceinline__ void begin(uint64_t base_lane, uint32_t cap_lane) {
+  __device__ __forceinline__ void begin(uint64_t base_lane, uint32_t cap_lane, uint32_t cls_lane) {
     base_l = base_lane;
     cap_l = cap_lane;
+    cls_l = cls_lane;
     p_l = wave_prefix((cap_lane + 63u) >> 6, np);
     p0 = 0;
   }
@@ -890,7 +900,13 @@ struct SegmentWalk {
     for (int u = 0; u < UR; ++u) {
       const uint32_t P = p0 + uint32_t(u);
       if (P >= np) {   // wave-uniform
-        if (COMP) r4[u] = 0u; else rec[u] = 0ull;
+        if (FMT == kFmtPlain) rec[u] = 0ull;
+        if (FMT == kFmtComp) r4[u] = 0u;
+        if (FMT == kFmtDev) {
+          r2[u] = 0u;
+          dv[u] = 0;
+          pc[u] = 0u;
+        }
         continue;
       }
       // Lanes past the last sender have p_l = np > P, so they never count.
@@ -900,26 +916,38 @@ struct SegmentWalk {
       const uint64_t base = join64(uint32_t(__builtin_amdgcn_readlane(uint32_t(base_l >> 32), s)),
                                    uint32_t(__builtin_amdgcn_readlane(uint32_t(base_l), s))) + 64u * k;
       const bool ok = 64u * k + lane < cap;
-      if (COMP)
-        r4[u] = ok ? __builtin_nontemporal_load(d.rec4 + base + lane) : 0u;
-      else
+      if (FMT == kFmtPlain) {
         rec[u] = ok ? __builtin_nontemporal_load(d.rec8 + base + lane) : 0ull;
+      } else if (FMT == kFmtComp) {
+        r4[u] = ok ? __builtin_nontemporal_load(d.rec4 + base + lane) : 0u;
+      } else {
+        r2[u] = ok ? uint32_t(__builtin_nontemporal_load(d.rec2 + base + lane)) : 0u;
+        dv[u] = ok ? int32_t(__builtin_nontemporal_load(d.dev8 + base + lane)) : 0;
+        pc[u] = uint32_t(__builtin_amdgcn_readlane(cls_l, s));
+      }
     }
     nv = min(np - p0, uint32_t(UR));
     p0 += UR;
   }
 
+  // dq / dsq: the deviation format's mean and step of (population, doubled pair).
   template <int WN>
-  __device__ __forceinline__ void apply(int32_t *s_ring, uint64_t t_src, uint32_t wb0) const {
+  __device__ __forceinline__ void apply(int32_t *s_ring, uint64_t t_src, uint32_t wb0,
+                                        const int32_t *dq, const int32_t *dsq) const {
 #pragma unroll
     for (int u = 0; u < UR; ++u) {
       if (uint32_t(u) >= nv) break;   // wave-uniform
       uint32_t delay, loc;
       int32_t wq;
-      if (COMP) {
+      if (FMT == kFmtComp) {
         delay = (r4[u] >> 10) & 63u;
         loc = r4[u] & 1023u;
         wq = int32_t(int16_t(uint16_t(r4[u] >> 16))) * 8;
+      } else if (FMT == kFmtDev) {
+        delay = (r2[u] >> 9) & 63u;
+        loc = r2[u] & 511u;
+        const uint32_t di = 2u * pc[u] + (r2[u] >> 15);
+        wq = dq[di] + dv[u] * dsq[di];
       } else {
         const uint32_t hiw = uint32_t(rec[u] >> 32);
         delay = hiw & 63u;
@@ -931,7 +959,7 @@ struct SegmentWalk {
   }
 };
 
-template <int WN, bool COMP>
+template <int WN, int FMT>
 __global__ __launch_bounds__(256) void k_lds(DeviceNet d, uint32_t n_steps, uint32_t group,
                                              uint32_t last_group, uint32_t win0,
                                              uint32_t spin_limit) {
@@ -951,6 +979,7 @@ __global__ __launch_bounds__(256) void k_lds(DeviceNet d, uint32_t n_steps, uint
   __shared__ __align__(16) uint32_t s_thr[8 * TS];
   __shared__ uint2 s_meta[8];
   __shared__ uint32_t s_cf[8], s_cn[8], s_ccap[8];   // sender classes
+  __shared__ int32_t s_dq[16], s_ds[16];      // deviation format: mean and step per (class, doubled)
   __shared__ uint64_t s_cbase[8];
   __shared__ uint32_t s_wstart[NZ];           // first neuron of each window of the instance
   __shared__ uint32_t s_sid[SB];              // senders of step t-1 (gid or list marker)
@@ -996,6 +1025,10 @@ __global__ __launch_bounds__(256) void k_lds(DeviceNet d, uint32_t n_steps, uint
     s_cbase[tid] = c.base;
   }
   if (tid < 4u) s_ctr[tid] = 0;
+  if (tid < 16u) {
+    s_dq[tid] = ip->dev_mq[tid];
+    s_ds[tid] = ip->dev_sq[tid];
+  }
   for (uint32_t i = tid; i < rel.y - rel.x; i += BS) s_wstart[i] = d.lwin[rel.x + i].x;
   // Thalamic tables of the window's instance.
   if (tid < 8u) {
@@ -1297,7 +1330,7 @@ __global__ __launch_bounds__(256) void k_lds(DeviceNet d, uint32_t n_steps, uint
       const uint32_t nb = min(SB, n_prev - j0);
       const uint32_t n_l = nb > wave ? (nb - wave + 3u) / 4u : 0u;
       uint64_t base_lane = 0;
-      uint32_t cap_lane = 0;
+      uint32_t cap_lane = 0, cls_lane = 0;
       if (lane < n_l) {
         // Senders of polling wave 0 come first, then those of wave 3.
         const uint32_t j = j0 + wave + 4u * lane;
@@ -1313,12 +1346,13 @@ __global__ __launch_bounds__(256) void k_lds(DeviceNet d, uint32_t n_steps, uint
           if (gid >= s_cf[c] && s_cn[c]) ci = uint32_t(c);
         cap_lane = gid - s_cf[ci] < s_cn[ci] ? s_ccap[ci] : 0u;
         base_lane = s_cbase[ci] + uint64_t(gid - s_cf[ci]) * cap_lane;
+        cls_lane = ci;
       }
-      SegmentWalk<COMP, UR> sw;
-      sw.begin(base_lane, cap_lane);
+      SegmentWalk<FMT, UR> sw;
+      sw.begin(base_lane, cap_lane, cls_lane);
       while (sw.more()) {
         sw.load(d);
-        sw.template apply<WN>(s_ring, tsrc, wb0v);
+        sw.template apply<WN>(s_ring, tsrc, wb0v, s_dq, s_ds);
       }
     }
     __syncthreads();
@@ -1370,14 +1404,16 @@ __global__ __launch_bounds__(256) void k_lds(DeviceNet d, uint32_t n_steps, uint
 
 using LdsFn = void (*)(DeviceNet, uint32_t, uint32_t, uint32_t, uint32_t, uint32_t);
 
-static LdsFn lds_fn(uint32_t wn, bool comp) {
-  if (wn == 512) return comp ? k_lds<512, true> : k_lds<512, false>;
-  if (wn == 320) return comp ? k_lds<320, true> : k_lds<320, false>;
+static LdsFn lds_fn(uint32_t wn, uint32_t syn_format) {
+  const int f = syn_format == SNN_SYN_COMPRESSED5 ? kFmtComp
+                                                  : (syn_format == SNN_SYN_DEV8 ? kFmtDev : kFmtPlain);
+  if (wn == 512) return f == kFmtComp ? k_lds<512, kFmtComp> : (f == kFmtDev ? k_lds<512, kFmtDev> : k_lds<512, kFmtPlain>);
+  if (wn == 320) return f == kFmtComp ? k_lds<320, kFmtComp> : (f == kFmtDev ? k_lds<320, kFmtDev> : k_lds<320, kFmtPlain>);
   return nullptr;
 }
 
 int lds_max_grid(uint32_t wn) {
-  LdsFn fn = lds_fn(wn, false);
+  LdsFn fn = lds_fn(wn, SNN_SYN_PLAIN8);
   if (!fn) return 0;
   int per_cu = 0, dev = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(fn), 256,
@@ -1390,7 +1426,7 @@ int lds_max_grid(uint32_t wn) {
 
 hipError_t launch_lds(const DeviceNet &d, uint32_t group, uint32_t n_groups, uint32_t win0,
                       uint32_t nwin, uint32_t n, hipStream_t s) {
-  LdsFn fn = lds_fn(d.lds_window, d.syn_format == SNN_SYN_COMPRESSED5);
+  LdsFn fn = lds_fn(d.lds_window, d.syn_format);
   if (!fn || nwin == 0 || nwin > kLdsMaxGrid || win0 + nwin > d.n_lwin || group >= n_groups)
     return hipErrorInvalidConfiguration;
   DeviceNet dv = d;

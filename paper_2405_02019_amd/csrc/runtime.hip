@@ -557,8 +557,11 @@ int snn_build(const snn_config *cfg, snn_net **out) {
                 SNN_ABI_VERSION);
   if (cfg->n_instances < 1 || cfg->n_instances > kMaxInstances || !cfg->inst)
     return fail(nullptr, SNN_E_INVAL, "need 1..%u instances", kMaxInstances);
-  if (cfg->syn_format > SNN_SYN_COMPRESSED5)
+  if (cfg->syn_format > SNN_SYN_DEV8)
     return fail(nullptr, SNN_E_INVAL, "unknown synapse format %u", cfg->syn_format);
+  if (cfg->syn_format == SNN_SYN_DEV8 && cfg->engine != SNN_ENGINE_AUTO &&
+      cfg->engine != SNN_ENGINE_LDS)
+    return fail(nullptr, SNN_E_INVAL, "the deviation format runs on the LDS engine only");
   if (cfg->engine > SNN_ENGINE_BAND)
     return fail(nullptr, SNN_E_INVAL, "unknown engine %u", cfg->engine);
   const auto t_start = std::chrono::steady_clock::now();
@@ -635,8 +638,9 @@ int snn_build(const snn_config *cfg, snn_net **out) {
       h->lds_groups = plan.groups;
       break;
     }
-    if (cfg->engine != SNN_ENGINE_AUTO) {
-      fail(h, prc, "%s", why.c_str());
+    if (cfg->engine != SNN_ENGINE_AUTO || cfg->syn_format == SNN_SYN_DEV8) {
+      fail(h, prc, "%s%s", cfg->syn_format == SNN_SYN_DEV8 ? "the deviation format needs the LDS engine: " : "",
+           why.c_str());
       return bail(prc);
     }
     h->engine = h->engine == SNN_ENGINE_LDS ? SNN_ENGINE_BAND : SNN_ENGINE_PERSISTENT;
@@ -713,7 +717,10 @@ int snn_build(const snn_config *cfg, snn_net **out) {
   uint32_t *d_rec4 = nullptr;
   int16_t *d_w16 = nullptr;
   uint8_t *d_d8 = nullptr;
+  uint16_t *d_rec2 = nullptr;
+  int8_t *d_dev8 = nullptr;
   const bool comp = cfg->syn_format == SNN_SYN_COMPRESSED5;
+  const bool devf = cfg->syn_format == SNN_SYN_DEV8;
   uint64_t cap = cfg->raster_capacity;
   // Default: room for the worst case of about 20,000 steps (a neuron spikes
   // at most every 21 steps), so that drains -- a stream synchronisation each
@@ -738,7 +745,10 @@ int snn_build(const snn_config *cfg, snn_net **out) {
   ALLOC(d.R4, d.nquads);
   ALLOC(d.W, size_t(kRing) * d.ntot);
   ALLOC(d_seg, nseg_tot + 1);
-  if (comp && lds_window) {
+  if (devf) {
+    ALLOC(d_rec2, std::max<uint64_t>(1, nrec_tot));
+    ALLOC(d_dev8, std::max<uint64_t>(1, nrec_tot));
+  } else if (comp && lds_window) {
     ALLOC(d_rec4, std::max<uint64_t>(1, nrec_tot));
   } else if (comp) {
     ALLOC(d_tgt16, std::max<uint64_t>(1, nrec_tot));
@@ -803,6 +813,8 @@ int snn_build(const snn_config *cfg, snn_net **out) {
     v.win_first = x.win_first;
     v.win_size = x.win_size;
     v.tbase0 = uint32_t(uint64_t(m.gbase) + uint64_t(x.win_first) * x.win_size - x.win_origin);
+    std::memcpy(v.dev_mq, x.dev_mq, sizeof v.dev_mq);
+    std::memcpy(v.dev_sq, x.dev_sq, sizeof v.dev_sq);
     for (uint32_t lq = 0; lq < m.npad / 4; ++lq) qinfo[m.gbase / 4 + lq] = (k << 24) | lq;
     std::copy(x.u0.begin(), x.u0.end(), u0.begin() + m.gbase);
     for (uint64_t s = 0; s + 1 < x.seg_ptr.size(); ++s) seg.push_back(syn_base + x.seg_ptr[s]);
@@ -869,7 +881,10 @@ int snn_build(const snn_config *cfg, snn_net **out) {
   syn_base = 0;
   for (uint32_t k = 0; k < ni; ++k) {
     HostInstance &x = hi[k];
-    if (comp && lds_window) {
+    if (devf) {
+      UPLOAD(d_rec2 + syn_base, x.rec2.data(), x.nrec * sizeof(uint16_t));
+      UPLOAD(d_dev8 + syn_base, x.dev8.data(), x.nrec * sizeof(int8_t));
+    } else if (comp && lds_window) {
       UPLOAD(d_rec4 + syn_base, x.rec4.data(), x.nrec * sizeof(uint32_t));
     } else if (comp) {
       UPLOAD(d_tgt16 + syn_base, x.tgt16.data(), x.nrec * sizeof(uint16_t));
@@ -895,6 +910,8 @@ int snn_build(const snn_config *cfg, snn_net **out) {
   d.seg_ptr = d_seg;
   d.rec8 = d_rec8;
   d.rec4 = d_rec4;
+  d.rec2 = d_rec2;
+  d.dev8 = d_dev8;
   d.tgt16 = d_tgt16;
   d.w16 = d_w16;
   d.d8 = d_d8;
@@ -1312,7 +1329,9 @@ std::vector<TuneCand> tune_candidates(const snn_config *cfg) {
     }
   };
   if (cfg->engine == SNN_ENGINE_AUTO || cfg->engine == SNN_ENGINE_LDS) family(SNN_ENGINE_LDS);
-  if (cfg->engine == SNN_ENGINE_AUTO || cfg->engine == SNN_ENGINE_BAND) family(SNN_ENGINE_BAND);
+  if ((cfg->engine == SNN_ENGINE_AUTO || cfg->engine == SNN_ENGINE_BAND) &&
+      cfg->syn_format != SNN_SYN_DEV8)
+    family(SNN_ENGINE_BAND);
   return out;
 }
 
@@ -1512,7 +1531,14 @@ int read_back(const HostInstance &x, uint32_t syn_format, snn_host_network **out
           uint32_t post, dl;
           int32_t wq;
           bool unused;
-          if (comp && x.band_h) {   // banded: weight << 16 | (delay - band_lo) << ob | offset
+          if (syn_format == SNN_SYN_DEV8) {   // doubled << 15 | delay << 9 | offset, deviation
+            const uint32_t r = x.rec2[e2];
+            const int di = int(2 * c + (r >> 15));
+            post = (x.win_first + w) * x.win_size + (r & 511u) - x.win_origin;
+            dl = (r >> 9) & 63u;
+            wq = x.dev_mq[di] + int32_t(x.dev8[e2]) * x.dev_sq[di];
+            unused = dl == 0;
+          } else if (comp && x.band_h) {   // banded: weight << 16 | (delay - band_lo) << ob | offset
             const uint32_t r = x.rec4[e2];
             post = w * x.win_size + (r & ((1u << ob) - 1u));
             dl = band_lo(b, x.band_h) + ((r & 0xFFFFu) >> ob);

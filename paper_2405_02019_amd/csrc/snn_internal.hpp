@@ -93,6 +93,8 @@ struct InstDev {
   uint32_t win_first;    // global index of the first of those windows
   uint32_t win_size;     // neurons per target window
   uint32_t tbase0;       // global id of the first target of window 0 of the instance
+  int32_t dev_mq[16];    // deviation format: mean weight of (sender population, doubled pair)
+  int32_t dev_sq[16];    // and its step, both in 2^-8 pA; index 2 * population + doubled
 };
 
 // FP32 propagators, computed in FP64 on the device (eqn:p11p22, eqn:p21).
@@ -136,6 +138,10 @@ struct HostInstance {
   std::vector<uint16_t> tgt16;       // compressed streams
   std::vector<int16_t> w16;
   std::vector<uint8_t> d8;
+  std::vector<uint16_t> rec2;        // deviation format: doubled << 15 | delay << 9 | offset
+  std::vector<int8_t> dev8;          // and the weight's deviation from its pair's mean
+  int32_t dev_mq[16] = {};           // mean weight of (sender population, doubled pair), 2^-8 pA
+  int32_t dev_sq[16] = {};           // deviation step of the same, 2^-8 pA
 };
 
 // Model (model.cpp).

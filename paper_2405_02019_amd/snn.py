@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(HERE, "libsnn.so")
 
 SYN_PLAIN8 = 0
 SYN_COMPRESSED5 = 1
+SYN_DEV8 = 2
 ENGINE_AUTO = 0
 ENGINE_STEPWISE = 1
 ENGINE_PERSISTENT = 2
@@ -179,7 +180,7 @@ class Instance:
 
 def _syn_format(fmt):
     if isinstance(fmt, str):
-        return {"plain": SYN_PLAIN8, "compressed": SYN_COMPRESSED5}[fmt]
+        return {"plain": SYN_PLAIN8, "compressed": SYN_COMPRESSED5, "dev8": SYN_DEV8}[fmt]
     return int(fmt)
 
 

@@ -25,10 +25,10 @@ def oracle():
 @pytest.fixture(scope="session")
 def full_scale_runs():
     """The full-scale microcircuit (seed 1) simulated for 10 s of biological
-    time (100,000 steps) on the GPU in the plain and the compressed synapse
-    formats, in the launch configuration the benchmark times (10,000-step
-    chunks).  Per format: the raster, the final state with the ring buffer,
-    and the library's launch description."""
+    time (100,000 steps) on the GPU in the plain, the compressed and the
+    deviation (dev8) synapse formats, in the launch configuration the
+    benchmark times (10,000-step chunks).  Per format: the raster, the final
+    state with the ring buffer, and the library's launch description."""
     import hashlib
 
     import numpy as np
@@ -38,7 +38,7 @@ def full_scale_runs():
         return hashlib.sha256(np.ascontiguousarray(a).tobytes()).hexdigest()
 
     out = {}
-    for fmt in ["plain", "compressed"]:
+    for fmt in ["plain", "compressed", "dev8"]:
         print(f"[full-scale run] {fmt}: 100000 steps in 10000-step launches", flush=True)
         with P.Simulator(P.Instance(scale=1.0, seed=1), syn_format=fmt, chunk_steps=10000) as sim:
             for k in range(10):

@@ -1,6 +1,7 @@
 """Writes the int32 oracle's fingerprints of 10 s of the full-scale
-microcircuit (seed 1), in the plain (2^-8 pA) and the compressed (16-bit,
-2^-5 pA) weight modes: the reference of the bit-exact GPU tests over the whole
+microcircuit (seed 1), in the plain (2^-8 pA), the compressed (16-bit,
+2^-5 pA) and the dev8 (pair mean plus an 8-bit deviation, Sec. 5.3) weight
+modes: the reference of the bit-exact GPU tests over the whole
 run (eqn:mem, eqn:psc, eqn:ref with the int32 input sum; Sec. 4.1 motivates
 spike-for-spike agreement).  Calls only the oracle.
 
@@ -13,7 +14,9 @@ Stored, per weight mode:
       and ring W (int64, 64 rows x N, row-major), the counters, the number
       of spikes, and the SHA-256 of the digest file's contents
 
-Usage: python tests/golden/make_int32_digests.py   (about 5 minutes)
+Usage: python tests/golden/make_int32_digests.py [mode ...]
+(about 4 minutes per mode; named modes are recomputed and merged into the
+existing JSON, no names recompute every mode)
 """
 import gzip
 import hashlib
@@ -33,7 +36,7 @@ from spike_stats import step_digest  # noqa: E402
 
 STEPS = 100_000
 SEED = 1
-MODES = {"plain": O.W_PLAIN, "compressed": O.W_COMPRESSED}
+MODES = {"plain": O.W_PLAIN, "compressed": O.W_COMPRESSED, "dev8": O.W_DEV8}
 BASENAME = "int32_full_scale_seed1"
 
 
@@ -41,10 +44,15 @@ def sha(a):
     return hashlib.sha256(np.ascontiguousarray(a).tobytes()).hexdigest()
 
 
-def main():
+def main(names):
     out = {"what": "int32 oracle, full-scale microcircuit, seed 1, 100000 steps of 0.1 ms",
            "seed": SEED, "scale": 1.0, "steps": STEPS, "modes": {}}
-    for name, wmode in MODES.items():
+    meta = os.path.join(HERE, f"{BASENAME}.json")
+    if names and os.path.exists(meta):
+        with open(meta) as f:
+            out = json.load(f)
+    for name in names or list(MODES):
+        wmode = MODES[name]
         t = time.time()
         net = O.Net(O.Config(scale=1.0, seed=SEED, weight_mode=wmode))
         sim = O.Sim(net).run(STEPS)
@@ -74,4 +82,4 @@ def main():
 
 
 if __name__ == "__main__":
-    main()
+    main(sys.argv[1:])

@@ -7,7 +7,7 @@ Sec. 4.1 asks for spike-for-spike agreement with the reference arithmetic.
 The oracle's per-step fingerprints and final-state hashes are stored in
 golden/int32_full_scale_seed1*.{json,digest.gz} (written by
 golden/make_int32_digests.py from the oracle alone).  The GPU runs in the
-benchmark's launch configuration (10,000-step chunks) in both synapse
+benchmark's launch configuration (10,000-step chunks) in all three synapse
 formats; the first step whose fingerprint differs is reported."""
 import gzip
 import hashlib
@@ -44,7 +44,7 @@ def golden():
 
 
 @pytest.mark.timeout(900)
-@pytest.mark.parametrize("fmt", ["plain", "compressed"])
+@pytest.mark.parametrize("fmt", ["plain", "compressed", "dev8"])
 def test_full_scale_10s_bit_exact(golden, full_scale_runs, fmt):
     meta, dig = golden
     m = meta["modes"][fmt]

@@ -371,6 +371,43 @@ def oracle_stub_instance():
     return P.Instance(scale=1.0, seed=1)
 
 
+@pytest.mark.parametrize("insts,chunk,pieces", [
+    ([(0.01, 7, -4.0)], 37, [1, 99, 100, 300]),
+    ([(0.05, 8, -4.0)], 100, [250, 50]),
+    ([(0.02, 9, -5.5), (0.01, 10, -3.0), (0.03, 11, -4.5)], 64, [130, 70]),
+])
+def test_dev8_bit_exact(P, oracle, insts, chunk, pieces):
+    """The deviation format (Sec. 5.3: each weight stored as its population
+    pair's mean plus an 8-bit deviation) on the LDS engine equals the oracle's
+    dev8 mode spike for spike, with the state and the whole ring, across
+    ragged launches; instances of different g carry their own means and
+    steps."""
+    inst = [P.Instance(scale=s, seed=sd, g=g) for s, sd, g in insts]
+    say("dev8", insts, chunk)
+    with P.Simulator(inst, syn_format="dev8", chunk_steps=chunk) as sim:
+        assert sim.info()["engine"] == P.ENGINE_LDS
+        for n in pieces:
+            sim.step(n)
+        total = 0
+        for k, x in enumerate(inst):
+            net, osim = run_oracle(oracle, x, 2, sum(pieces))
+            total += assert_parity(sim, k, net, osim)
+    assert total > 1000
+
+
+def test_dev8_full_scale_window_bit_exact(P, oracle):
+    """Full scale in the benchmark's launch length (10,000-step chunks), the
+    first 300 steps in the deviation format, against the oracle's dev8 mode."""
+    inst = oracle_stub_instance()
+    with P.Simulator(inst, syn_format="dev8", chunk_steps=10000) as sim:
+        assert sim.info()["engine"] == P.ENGINE_LDS
+        sim.step(300)
+        net, osim = run_oracle(oracle, inst, 2, 300)
+        n = assert_parity(sim, 0, net, osim)
+        say("dev8 full scale spikes", n)
+    assert n > 5000
+
+
 @pytest.mark.parametrize("engine", ["stepwise", "persistent", "lds", "band"])
 def test_full_scale_window_bit_exact(P, full_oracle, engine):
     """Full-scale microcircuit (77,169 neurons, 2.99e8 synapses): the first

@@ -118,7 +118,7 @@ def test_sampler_equals_oracle(P, oracle, fmt, wmode, scale, mode, seed):
 
 
 @pytest.mark.parametrize("window", [256, 512])
-@pytest.mark.parametrize("fmt,wmode", [("plain", 0), ("compressed", 1)])
+@pytest.mark.parametrize("fmt,wmode", [("plain", 0), ("compressed", 1), ("dev8", 2)])
 def test_windowed_layout_holds_the_oracle_network(P, oracle, window, fmt, wmode):
     """The LDS engine's layout (fixed-capacity segments per sender and target
     window, unused slots marked by delay 0) read back gives every row of the
@@ -170,6 +170,30 @@ def test_banded_layout_holds_the_oracle_network(P, oracle, window, ring_rows, fm
     same_row = pre[1:] == pre[:-1]
     assert np.all(key[1:][same_row] >= key[:-1][same_row])
     assert band.max() <= (62 + ring_rows - 1) // ring_rows and band.max() >= 1
+
+
+def test_dev8_format_is_for_the_lds_layout_only(P):
+    """The deviation format (Sec. 5.3) is stored for the LDS engine: the other
+    layouts and engines refuse it instead of quantising differently."""
+    inst = P.Instance(scale=0.01)
+    with pytest.raises(P.SnnError, match="INVAL"):
+        P.sample_network(inst, "dev8")
+    with pytest.raises(P.SnnError, match="INVAL"):
+        P.sample_network(inst, "dev8", window=256, ring_rows=16)
+    S = P.snn
+    L = P.lib()
+    h = C.c_void_p()
+    cfg = S._Cfg()
+    L.snn_config_default(C.byref(cfg))
+    ci = S._Inst()
+    L.snn_instance_default(C.byref(ci))
+    cfg.inst = C.pointer(ci)
+    cfg.syn_format = S.SYN_DEV8
+    for engine in [S.ENGINE_PERSISTENT, S.ENGINE_STEPWISE, S.ENGINE_BAND]:
+        cfg.engine = engine
+        assert L.snn_build(C.byref(cfg), C.byref(h)) == -1   # checked before any device call
+        assert b"LDS engine only" in L.snn_last_error(None)
+        assert not h
 
 
 def test_banded_layout_rejects_bad_shapes(P):
