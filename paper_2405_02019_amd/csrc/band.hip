@@ -228,7 +228,10 @@ struct BandWalk {
   __device__ __forceinline__ void apply(int32_t *s_ring, uint32_t wb0) const {
 #pragma unroll
     for (int u = 0; u < UR; ++u) {
-      if (uint32_t(u) >= nv) break;   // wave-uniform
+      if (uint32_t(u) >= nv) {   // wave-uniform; past 8 slots the compiler unrolls
+        if (UR > 8) continue;    // only a loop without an early exit
+        break;
+      }
       int32_t w;
       uint32_t row, loc;
       decode<COMP, H>(COMP ? 0ull : rec[u], COMP ? r4[u] : 0u, rbv[u], wb0, w, row, loc);
@@ -244,7 +247,10 @@ struct BandWalk {
                                               uint32_t t_end) const {
 #pragma unroll
     for (int u = 0; u < UR; ++u) {
-      if (uint32_t(u) >= nv) break;
+      if (uint32_t(u) >= nv) {   // wave-uniform; past 8 slots the compiler unrolls
+        if (UR > 8) continue;    // only a loop without an early exit
+        break;
+      }
       int32_t w;
       uint32_t row, loc;
       decode<COMP, H>(COMP ? 0ull : rec[u], COMP ? r4[u] : 0u, rbv[u], wb0, w, row, loc);
@@ -272,7 +278,7 @@ __global__ __launch_bounds__(BS) void k_band(DeviceNet d, uint32_t n_steps, uint
   constexpr uint32_t NZH = NZ / 2;             // windows polled by one wave
   constexpr uint32_t RC = 640;                 // raster staging entries
   constexpr uint32_t SB = 64 * NW;             // senders resolved per round
-  constexpr int UR = BS >= 1024 ? 4 : 8;       // loads in flight per lane (register budget)
+  constexpr int UR = BS >= 1024 ? 4 : (BS == 512 ? 16 : 8);   // loads in flight per lane
   constexpr bool PACK = BS == 512;             // packed walk (the variant of the widest bands)
   static_assert(Q0 >= 128, "waves 0 and 1 own no quad");
   static_assert(NSLOT > LOMAX, "the history must reach the last slow band");
