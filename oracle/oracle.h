@@ -156,6 +156,9 @@ int orc_sim_set_probes(orc_sim *s, const uint32_t *ids, uint32_t n);
  * (tiny networks only: 12 bytes per neuron per step). */
 int orc_sim_record_inputs(orc_sim *s, int on);
 int orc_sim_run(orc_sim *s, uint64_t n_steps);
+/* The same loop (INT32 arithmetic only, no probes or recording) on `threads`
+ * host threads; equal to orc_sim_run bit for bit.  A CPU baseline. */
+int orc_sim_run_threads(orc_sim *s, uint64_t n_steps, int threads);
 
 uint64_t orc_sim_t(const orc_sim *s);
 void orc_sim_counters(const orc_sim *s, orc_counters *c);

@@ -94,6 +94,7 @@ def lib():
         L.orc_sim_set_probes.argtypes = [vp, C.POINTER(C.c_uint32), C.c_uint32]
         L.orc_sim_record_inputs.argtypes = [vp, C.c_int]
         L.orc_sim_run.argtypes = [vp, C.c_uint64]
+        L.orc_sim_run_threads.argtypes = [vp, C.c_uint64, C.c_int]
         L.orc_sim_t.argtypes = [vp]
         L.orc_sim_t.restype = C.c_uint64
         L.orc_sim_counters.argtypes = [vp, C.POINTER(_Counters)]
@@ -328,6 +329,12 @@ class Sim:
 
     def run(self, n_steps):
         _check(lib().orc_sim_run(self.h, int(n_steps)))
+        return self
+
+    def run_threads(self, n_steps, threads):
+        """The same steps on `threads` host threads (INT32 arithmetic; a CPU
+        baseline, equal to run() bit for bit)."""
+        _check(lib().orc_sim_run_threads(self.h, int(n_steps), int(threads)))
         return self
 
     @property

@@ -319,6 +319,98 @@ int orc_sim_run(orc_sim *s, uint64_t n_steps) {
   return ORC_OK;
 }
 
+/* The step loop of orc_sim_run for the INT32 arithmetic on several host
+ * threads (OpenMP), as a CPU baseline on all cores; orc_sim_run stays the
+ * checker.  Neurons are updated in parallel (four per Philox block, as
+ * above), the senders of the step are collected in id order, and their
+ * synapses are delivered in parallel with atomic adds into the int64 ring.
+ * Each ring entry is an exact integer sum, so the results equal
+ * orc_sim_run's bit for bit whatever the thread count.  Probes and input
+ * recording are not supported (ORC_E_INVAL); an int32 overflow is reported
+ * after the update phase of its step. */
+int orc_sim_run_threads(orc_sim *s, uint64_t n_steps, int threads) {
+  if (s->arith != ORC_ARITH_INT32 || s->rec_on || s->nprobe || threads < 1) return ORC_E_INVAL;
+  const orc_net *n = s->net;
+  const orc_consts *k = &n->k;
+  const uint32_t N = s->N;
+  const uint64_t seed = n->cfg.seed;
+  const long long nq = (long long)((N + 3u) / 4u);
+  uint8_t *fl = (uint8_t *)calloc(N ? N : 1, 1);
+  if (!fl) return ORC_E_NOMEM;
+  for (uint64_t step = 0; step < n_steps; ++step) {
+    const uint64_t t = s->t;
+    const uint32_t row = (uint32_t)(t & (ORC_D_MAX - 1));
+    int overflow = 0;
+    int64_t consumed = 0;
+    uint64_t poisson = 0;
+#pragma omp parallel for num_threads(threads) schedule(static) reduction(+ : consumed, poisson) \
+    reduction(| : overflow)
+    for (long long qd = 0; qd < nq; ++qd) {
+      uint32_t blk[4];
+      orc_draw(seed, (uint32_t)qd, (uint32_t)t, (uint32_t)(t >> 32), ORC_TAG_POI, blk);
+      const uint32_t i0 = 4u * (uint32_t)qd, i1 = i0 + 4u < N ? i0 + 4u : N;
+      for (uint32_t i = i0; i < i1; ++i) {
+        const int T = thalamic(n, i, blk);
+        const int spike = membrane_f32(&s->U[i], &s->R[i], s->I[i], k);
+        int64_t *slot = &s->ring[(size_t)row * N + i];
+        const int64_t q = (int64_t)T * k->w_ext_q + *slot;
+        if (q > 2147483647LL || q < -2147483647LL - 1) overflow = 1;
+        consumed += *slot;
+        *slot = 0;
+        s->I[i] = current_f32(s->I[i], q, k);
+        poisson += (uint64_t)T;
+        fl[i] = (uint8_t)spike;
+      }
+    }
+    if (overflow) {
+      free(fl);
+      orc_error("input of a neuron at step %llu overflows int32", (unsigned long long)t);
+      return ORC_E_OVERFLOW;
+    }
+    s->cnt.consumed += consumed;
+    s->cnt.poisson += poisson;
+    uint32_t nspk = 0;
+    for (uint32_t i = 0; i < N; ++i) {
+      if (!fl[i]) continue;
+      s->spk[nspk++] = i;
+      if (s->nr == s->cap_r) {
+        uint64_t nc = s->cap_r ? 2 * s->cap_r : 4096;
+        uint32_t *a = (uint32_t *)realloc(s->r_step, (size_t)nc * sizeof(uint32_t));
+        if (!a) { free(fl); return ORC_E_NOMEM; }
+        s->r_step = a;
+        a = (uint32_t *)realloc(s->r_id, (size_t)nc * sizeof(uint32_t));
+        if (!a) { free(fl); return ORC_E_NOMEM; }
+        s->r_id = a;
+        s->cap_r = nc;
+      }
+      s->r_step[s->nr] = (uint32_t)t;
+      s->r_id[s->nr] = i;
+      s->nr += 1;
+    }
+    int64_t injected = 0;
+    uint64_t events = 0;
+#pragma omp parallel for num_threads(threads) schedule(dynamic, 1) reduction(+ : injected, events)
+    for (long long qq = 0; qq < (long long)nspk; ++qq) {
+      const uint32_t src = s->spk[qq];
+      const uint64_t e0 = n->row_ptr[src], e1 = n->row_ptr[src + 1];
+      events += e1 - e0;
+      for (uint64_t e = e0; e < e1; ++e) {
+        const uint32_t r2 = (uint32_t)((t + n->delay[e]) & (ORC_D_MAX - 1));
+        int64_t *dst = &s->ring[(size_t)r2 * N + n->post[e]];
+#pragma omp atomic
+        *dst += n->w_q[e];
+        injected += n->w_q[e];
+      }
+    }
+    s->cnt.events += events;
+    s->cnt.injected += injected;
+    s->cnt.spikes += nspk;
+    s->t = t + 1;
+  }
+  free(fl);
+  return ORC_OK;
+}
+
 uint64_t orc_sim_t(const orc_sim *s) { return s->t; }
 void orc_sim_counters(const orc_sim *s, orc_counters *c) { *c = s->cnt; }
 uint64_t orc_sim_nspikes(const orc_sim *s) { return s->nr; }

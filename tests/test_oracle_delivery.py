@@ -161,6 +161,35 @@ def test_pull_brute_force_reproduces_push_dev8(oracle):
     np.testing.assert_array_equal(st["I"], I)
 
 
+@pytest.mark.parametrize("scale,seed,steps,threads", [(0.05, 12, 600, 4), (0.01, 13, 900, 3)])
+def test_threaded_step_loop_equals_serial(oracle, scale, seed, steps, threads):
+    """The all-cores baseline loop (neurons in parallel, atomic int64 ring
+    adds) gives the serial loop's raster, state, ring and counters bit for
+    bit: every ring entry is an exact integer sum."""
+    net = oracle.Net(oracle.Config(scale=scale, seed=seed))
+    a = oracle.Sim(net).run(steps)
+    b = oracle.Sim(net).run_threads(steps // 3, threads).run_threads(steps - steps // 3, threads)
+    sa, ia = a.raster()
+    sb, ib = b.raster()
+    assert len(sa) > 1000
+    np.testing.assert_array_equal(sa, sb)
+    np.testing.assert_array_equal(ia, ib)
+    x, y = a.state(), b.state()
+    for k in ["U", "I", "R", "W"]:
+        np.testing.assert_array_equal(x[k], y[k])
+    assert a.counters() == b.counters()
+
+
+def test_threaded_step_loop_refuses_what_it_does_not_do(oracle):
+    net = oracle.Net(oracle.Config(scale=0.01, seed=1))
+    with pytest.raises(oracle.OracleError):
+        oracle.Sim(net, arith=oracle.ARITH_F64).run_threads(10, 2)
+    with pytest.raises(oracle.OracleError):
+        oracle.Sim(net, record_inputs=True).run_threads(10, 2)
+    with pytest.raises(oracle.OracleError):
+        oracle.Sim(net).run_threads(10, 0)
+
+
 def test_delivered_events_and_charge_conservation(oracle, tiny):
     """Every spike activates each outgoing synapse exactly once: delivered
     events = sum of sender out-degrees, and the charge injected equals what
