@@ -162,6 +162,10 @@ struct BandWalk {
   __device__ __forceinline__ bool more() const { return u0 < nu; }
 
   __device__ __forceinline__ void load(const DeviceNet &d) {
+    if constexpr (PACK) {
+      load_packed(d);
+      return;
+    }
     const uint32_t lane = __lane_id();
 #pragma unroll
     for (int u = 0; u < UR; ++u) {
@@ -194,29 +198,68 @@ struct BandWalk {
                       uint32_t(__builtin_amdgcn_readlane(uint32_t(base_l), s))) + off;
         ok = off < cap;
       } else {
-        // Largest lane s with p_s <= slot: a slot below the total lies in a
-        // segment of positive capacity, so s is a real sender and the slot's
-        // offset in it is below its capacity.
-        const uint32_t slot = 64u * U + lane;
-        uint32_t s = 0, ps = 0;
-#pragma unroll
-        for (uint32_t step = 32; step; step >>= 1) {
-          const uint32_t c = s + step;
-          const uint32_t pc = __shfl(p_l, int(c));
-          const bool le = pc <= slot;
-          s = le ? c : s;
-          ps = le ? pc : ps;
-        }
-        const uint32_t blo = __shfl(uint32_t(base_l), int(s));
-        const uint32_t bhi = __shfl(uint32_t(base_l >> 32), int(s));
-        rbv[u] = __shfl(rb_l, int(s));
-        addr = join64(bhi, blo) + (slot - ps);
-        ok = slot < total;
+        addr = 0;
+        ok = false;
       }
       if (COMP) {
         if (ok) r4[u] = __builtin_nontemporal_load(d.rec4 + addr);
       } else {
         if (ok) rec[u] = __builtin_nontemporal_load(d.rec8 + addr);
+      }
+    }
+    nv = min(nu - u0, uint32_t(UR));
+    u0 += UR;
+  }
+
+  // Packed walk: slot 64 U + lane of the batch belongs to the largest lane
+  // s with p_s <= slot (a slot below the total lies in a segment of positive
+  // capacity, so s is a real sender and the slot's offset in it is below its
+  // capacity).  The six-level binary searches of PG units run interleaved:
+  // each level is a cross-lane read whose latency the other units' reads
+  // hide.  The first level compares with lane 32 for every slot.
+  __device__ __forceinline__ void load_packed(const DeviceNet &d) {
+    constexpr int PG = 4;
+    static_assert(UR % PG == 0, "units per round: a multiple of the search group");
+    const uint32_t lane = __lane_id();
+    const uint32_t p32 = uint32_t(__builtin_amdgcn_readlane(p_l, 32));
+#pragma unroll
+    for (int g = 0; g < UR; g += PG) {
+#pragma unroll
+      for (int v = 0; v < PG; ++v) {
+        if (COMP) r4[g + v] = 0u; else rec[g + v] = 0ull;
+        rbv[g + v] = 0;
+      }
+      if (u0 + uint32_t(g) >= nu) continue;   // wave-uniform
+      uint32_t sv[PG], ps[PG], slot[PG];
+#pragma unroll
+      for (int v = 0; v < PG; ++v) {
+        slot[v] = 64u * (u0 + uint32_t(g + v)) + lane;
+        const bool le = p32 <= slot[v];
+        sv[v] = le ? 32u : 0u;
+        ps[v] = le ? p32 : 0u;
+      }
+#pragma unroll
+      for (uint32_t step = 16; step; step >>= 1) {
+        uint32_t pc[PG];
+#pragma unroll
+        for (int v = 0; v < PG; ++v) pc[v] = __shfl(p_l, int(sv[v] + step));
+#pragma unroll
+        for (int v = 0; v < PG; ++v) {
+          const bool le = pc[v] <= slot[v];
+          sv[v] = le ? sv[v] + step : sv[v];
+          ps[v] = le ? pc[v] : ps[v];
+        }
+      }
+#pragma unroll
+      for (int v = 0; v < PG; ++v) {
+        const uint32_t blo = __shfl(uint32_t(base_l), int(sv[v]));
+        const uint32_t bhi = __shfl(uint32_t(base_l >> 32), int(sv[v]));
+        rbv[g + v] = __shfl(rb_l, int(sv[v]));
+        const uint64_t addr = join64(bhi, blo) + (slot[v] - ps[v]);
+        if (slot[v] < total) {
+          if (COMP) r4[g + v] = __builtin_nontemporal_load(d.rec4 + addr);
+          else rec[g + v] = __builtin_nontemporal_load(d.rec8 + addr);
+        }
       }
     }
     nv = min(nu - u0, uint32_t(UR));
@@ -387,6 +430,11 @@ __global__ __launch_bounds__(BS) void k_band(DeviceNet d, uint32_t n_steps, uint
   asm volatile("" : "+v"(seed), "+v"(k.p11), "+v"(k.p22), "+v"(k.p21), "+v"(wext), "+v"(wb0v));
   uint32_t *llist_v = d.llist;
   uint32_t *ghist_v = d.ghist;
+  // The 1,024-thread variant (windows of small instances, rarely more than
+  // HC senders a step) keeps no private history: its registers are spent.
+  constexpr uint32_t PH = BS >= 1024 ? 0u : kBandPrivHist;
+  uint32_t *phist_v = PH ? d.phist + size_t(blk) * 64u * PH : nullptr;
+  if constexpr (PH > 0) asm volatile("" : "+v"(phist_v));
   uint64_t *raster_v = d.raster;
   Control *ctl_v = d.ctl;
   uint64_t rcap_v = d.raster_cap;
@@ -473,9 +521,12 @@ __global__ __launch_bounds__(BS) void k_band(DeviceNet d, uint32_t n_steps, uint
       if (gid >= s_cf[c] && s_cn[c]) ci = uint32_t(c);
     return ci;
   };
-  // Sender k of step s from the history.
+  // Sender k of step s from the history: the first HC in LDS, the next PH
+  // in the block's own device memory (written and read by this block only,
+  // ordered by its barriers), the rest in the instance's shared history.
   auto hist = [&](uint64_t s, uint32_t kk) -> uint32_t {
     if (kk < uint32_t(HC)) return s_hist[uint32_t(s % NSLOT) * HC + kk];
+    if (kk < uint32_t(HC) + PH) return phist_v[(size_t(s & 63u)) * PH + (kk - uint32_t(HC))];
     return ld_ag(ghist_v + size_t(s & 63u) * ntot_v + gbase_v + kk);
   };
 
@@ -735,6 +786,8 @@ __global__ __launch_bounds__(BS) void k_band(DeviceNet d, uint32_t n_steps, uint
                                                 s_nzp + NZH * hs, s_nzb + NZH * hs, s_wstart);
         if (j < uint32_t(HC))
           s_hist[hslot * HC + j] = gid;
+        else if (j < uint32_t(HC) + PH)
+          phist_v[size_t(tsrc & 63u) * PH + (j - uint32_t(HC))] = gid;
         else
           st_ag(ghist_v + size_t(tsrc & 63u) * ntot_v + gbase_v + j, gid);
         const uint32_t ci = sender_class(gid);

@@ -17,6 +17,11 @@ constexpr uint32_t kMetaLds = 512;
 // LDS copies hold, and sender classes (the populations of the window's
 // instance) a window receives from.
 constexpr uint32_t kLdsMaxGrid = 256;
+// Banded engine, variants of fewer than 1,024 threads: sender ids per step a
+// block keeps in device memory of its own after its LDS history (read back
+// through its own XCD's L2; the ids past these come from the shared history
+// at device scope).
+constexpr uint32_t kBandPrivHist = 192;
 constexpr uint32_t kLdsTab = 32;
 constexpr uint32_t kWinClasses = 8;
 // Flag and list slots of the LDS engine: a block publishes step t only after
@@ -98,7 +103,11 @@ struct DeviceNet {
   uint32_t *llist = nullptr;        // LDS engine: [kSlots][ntot] senders beyond the inline ones
   uint32_t band_h = 0;              // banded engine: ring rows in LDS (64, 16 or 8), else 0
   uint32_t *ghist = nullptr;        // banded engine: [64][ntot] sender ids of each step beyond
-                                    // the block's LDS history (same values from every block)
+                                    // the block's LDS and private history (same values from
+                                    // every block)
+  uint32_t *phist = nullptr;        // banded engine below 1,024 threads: [blocks][64][kBandPrivHist]
+                                    // the block's own sender ids of each step past its LDS
+                                    // history
 };
 
 struct LaunchShape {

@@ -769,7 +769,11 @@ int snn_build(const snn_config *cfg, snn_net **out) {
   uint2 *d_wrel = nullptr;
   uint4 *d_lwin = nullptr;
   uint32_t *d_outdeg = nullptr;
-  if (banded) ALLOC(d.ghist, size_t(64) * d.ntot);
+  if (banded) {
+    ALLOC(d.ghist, size_t(64) * d.ntot);
+    if (kBandVariants[h->band_variant].block < 1024)
+      ALLOC(d.phist, size_t(nwin_lds) * 64 * kBandPrivHist);
+  }
   if (lds_window) {
     ALLOC(d_wcls, size_t(nwin_lds) * nband * kWinClasses);
     ALLOC(d_wrel, nwin_lds);
@@ -1021,8 +1025,9 @@ int snn_step_n_noalloc(snn_net *h, uint64_t n_steps, uint64_t *d_raster, uint64_
   const size_t nflags = size_t(kSlots) * d.n_lwin;
   const size_t b_ctl = round256(sizeof(Control)), b_grp = 256, b_flags = round256(nflags * 8),
                b_list = round256(size_t(kSlots) * d.ntot * 4),
-               b_hist = d.ghist ? round256(size_t(64) * d.ntot * 4) : 0;
-  const size_t need = b_ctl + b_grp + b_flags + b_list + b_hist;
+               b_hist = d.ghist ? round256(size_t(64) * d.ntot * 4) : 0,
+               b_phist = d.phist ? round256(size_t(d.n_lwin) * 64 * kBandPrivHist * 4) : 0;
+  const size_t need = b_ctl + b_grp + b_flags + b_list + b_hist + b_phist;
   if (need > kScratchBytes)
     return fail(h, SNN_E_RANGE, "the network needs %zu bytes of scratch, the static area holds %zu",
                 need, kScratchBytes);
@@ -1036,6 +1041,8 @@ int snn_step_n_noalloc(snn_net *h, uint64_t n_steps, uint64_t *d_raster, uint64_
   dv.lflags = reinterpret_cast<uint64_t *>(p + b_ctl + b_grp);
   dv.llist = reinterpret_cast<uint32_t *>(p + b_ctl + b_grp + b_flags);
   dv.ghist = d.ghist ? reinterpret_cast<uint32_t *>(p + b_ctl + b_grp + b_flags + b_list) : nullptr;
+  dv.phist = d.phist ? reinterpret_cast<uint32_t *>(p + b_ctl + b_grp + b_flags + b_list + b_hist)
+                     : nullptr;
   dv.raster = d_raster;
   dv.raster_cap = raster_cap;
   hipLaunchKernelGGL(k_noalloc_begin, dim3(1), dim3(256), 0, h->stream, dv.ctl, d.ctl, dv.lflags,
