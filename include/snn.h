@@ -33,7 +33,7 @@
 extern "C" {
 #endif
 
-#define SNN_ABI_VERSION 3u
+#define SNN_ABI_VERSION 4u
 
 enum snn_status {
   SNN_OK = 0,
@@ -126,6 +126,14 @@ typedef struct {
   uint32_t window_neurons;     /* LDS engines: neurons per window (a multiple of
                                   4); 0 = the shortest that fills one launch     */
   uint32_t reserved0;          /* 0                                              */
+  const uint32_t *inst_window_neurons;
+                               /* LDS engines: NULL, or one window length per
+                                  instance (n_instances entries, multiples of 4,
+                                  window_neurons = 0): an instance that fires
+                                  more gets shorter windows, so that every block
+                                  delivers about as many synaptic events a step
+                                  (snn_build_tuned derives them from measured
+                                  event counts); read during the call only      */
   void *hip_stream;            /* hipStream_t; NULL = a stream of the library    */
   void *(*dev_alloc)(size_t bytes, void *ctx); /* NULL = hipMalloc              */
   void (*dev_free)(void *ptr, void *ctx);
@@ -317,11 +325,18 @@ int snn_autotune(snn_net *h, uint32_t trial_steps, snn_tune_report *out);
  * that fills one launch, and longer ones up to the kernel's capacity: fewer,
  * larger destination classes of Sec. 3.6) -- is built, run for trial_steps / 4
  * warm-up and trial_steps timed steps, and the fastest is built again from
- * step 0 and returned in *out.  Results do not depend on the choice.
+ * step 0 and returned in *out.  With several instances, the first candidate's
+ * run also counts each instance's synaptic events per neuron and step, and
+ * the winner's kernel is timed once more with per-instance window lengths
+ * (inst_window_neurons) that give every block about the same events per step.
+ * Results do not depend on the choice.
  *   cache_path: NULL, or a text file of earlier choices keyed by the GPU's
- *   architecture name and a digest of the configuration; a hit builds the
- *   cached choice without timing (rep->candidates = 0), a miss appends the
- *   new choice.  Other engines: as snn_build (no candidates).
+ *   architecture name and a digest of the configuration (one line each:
+ *   architecture, digest, engine, window length, best and first us per step,
+ *   and per-instance window lengths joined by commas when those won); a hit
+ *   builds the cached choice without timing (rep->candidates = 0), a miss
+ *   appends the new choice.  Configurations that fix window_neurons or
+ *   inst_window_neurons, and other engines: as snn_build (no candidates).
  * Errors: as snn_build and snn_step_n; SNN_E_INVAL for trial_steps = 0.
  */
 int snn_build_tuned(const snn_config *cfg, uint32_t trial_steps, const char *cache_path,

@@ -274,12 +274,16 @@ uint32_t quads_of(const InstMeta &m) { return (m.n + 3) / 4; }
 
 uint32_t windows_for(uint32_t nq, uint32_t L) { return (nq + L / 4 - 1) / (L / 4); }
 
-bool make_plan(const std::vector<InstMeta> &im, uint32_t L, uint32_t wn, uint32_t maxg,
-               LdsPlan &p) {
+// Ls: the window length of each instance.
+bool make_plan(const std::vector<InstMeta> &im, const std::vector<uint32_t> &Ls, uint32_t wn,
+               uint32_t maxg, LdsPlan &p) {
   p = LdsPlan();
   p.wn = wn;
   uint32_t g0 = 0, gsize = 0;
-  for (const InstMeta &m : im) {
+  for (size_t k = 0; k < im.size(); ++k) {
+    const InstMeta &m = im[k];
+    const uint32_t L = Ls[k];
+    if (L < 4 || L > wn) return false;
     const uint32_t nq = quads_of(m);
     const uint32_t nw0 = windows_for(nq, L);
     if (nw0 == 0) return false;
@@ -300,8 +304,46 @@ bool make_plan(const std::vector<InstMeta> &im, uint32_t L, uint32_t wn, uint32_
   return true;
 }
 
+bool make_plan(const std::vector<InstMeta> &im, uint32_t L, uint32_t wn, uint32_t maxg,
+               LdsPlan &p) {
+  return make_plan(im, std::vector<uint32_t>(im.size(), L), wn, maxg, p);
+}
+
+// Window lengths that even out the synaptic events a block delivers per step
+// (the destination classes of Sec. 3.6 sized by load): instance k, with w[k]
+// events per neuron and step, gets windows of about T / w[k] neurons (at most
+// wn, the kernel's capacity; silent instances get wn), for the smallest T
+// whose windows fit maxg blocks.  False when even wn-neuron windows do not.
+bool balanced_lengths(const std::vector<InstMeta> &im, const std::vector<double> &w, uint32_t wn,
+                      uint32_t maxg, std::vector<uint32_t> &L) {
+  const size_t n = im.size();
+  L.assign(n, wn);
+  auto lengths = [&](double T, std::vector<uint32_t> &out) {
+    uint64_t total = 0;
+    for (size_t k = 0; k < n; ++k) {
+      uint32_t l = wn;
+      if (w[k] > 0.0 && T / w[k] < double(wn)) l = std::max(4u, uint32_t(T / w[k]) & ~3u);
+      out[k] = l;
+      total += windows_for(quads_of(im[k]), l);
+    }
+    return total;
+  };
+  double wmax = 0.0;
+  for (double x : w) wmax = std::max(wmax, x);
+  std::vector<uint32_t> tmp(n);
+  if (lengths(wmax * wn, L) > maxg) return false;
+  if (wmax <= 0.0) return true;
+  double lo = 0.0, hi = wmax * wn;
+  for (int it = 0; it < 64; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (lengths(mid, tmp) <= maxg) hi = mid; else lo = mid;
+  }
+  lengths(hi, L);
+  return true;
+}
+
 int plan_lds(const std::vector<InstMeta> &im, uint32_t block, uint32_t grid, uint32_t want_L,
-             bool allow_groups, LdsPlan &p, std::string &why) {
+             const uint32_t *each_L, bool allow_groups, LdsPlan &p, std::string &why) {
   if (block && block != 256) {
     why = "the LDS engine runs 256-thread blocks";
     return SNN_E_INVAL;
@@ -309,6 +351,17 @@ int plan_lds(const std::vector<InstMeta> &im, uint32_t block, uint32_t grid, uin
   const int g320 = lds_max_grid(320), g512 = lds_max_grid(512);
   if (g320 <= 0 || g512 <= 0) {
     why = "the LDS kernel cannot be made co-resident on this device";
+    return SNN_E_RANGE;
+  }
+  if (each_L) {   // one window length per instance
+    const std::vector<uint32_t> Ls(each_L, each_L + im.size());
+    const uint32_t Lmax = *std::max_element(Ls.begin(), Ls.end());
+    const uint32_t wn = Lmax <= 320 ? 320 : 512;
+    const uint32_t maxg = uint32_t(wn == 320 ? g320 : g512);
+    if (Lmax <= 512 && make_plan(im, Ls, wn, maxg, p) && p.groups.size() == 1 &&
+        (!grid || p.total == grid))
+      return SNN_OK;
+    why = "the per-instance window lengths do not fit one launch of the LDS engine";
     return SNN_E_RANGE;
   }
   if (want_L) {   // the requested window length
@@ -351,7 +404,7 @@ int plan_lds(const std::vector<InstMeta> &im, uint32_t block, uint32_t grid, uin
 // shortest window (at least 256 neurons) that put every instance into one
 // co-resident launch; a requested grid size fixes the number of windows.
 int plan_band(const std::vector<InstMeta> &im, uint32_t block, uint32_t grid, uint32_t want_L,
-              LdsPlan &p, uint32_t &variant, std::string &why) {
+              const uint32_t *each_L, LdsPlan &p, uint32_t &variant, std::string &why) {
   uint64_t nq = 0;
   for (const InstMeta &m : im) nq += quads_of(m);
   for (uint32_t v = 0; v < kNumBandVariants; ++v) {
@@ -360,6 +413,14 @@ int plan_band(const std::vector<InstMeta> &im, uint32_t block, uint32_t grid, ui
     const int g = band_max_grid(v);
     if (g <= 0) continue;
     const uint32_t maxg = uint32_t(g);
+    if (each_L) {   // one window length per instance, the first variant holding them
+      const std::vector<uint32_t> Ls(each_L, each_L + im.size());
+      if (make_plan(im, Ls, bv.wn, maxg, p) && p.groups.size() == 1 && (!grid || p.total == grid)) {
+        variant = v;
+        return SNN_OK;
+      }
+      continue;
+    }
     if (want_L) {   // the requested window length, with the first variant holding it
       const uint32_t L = want_L & ~3u;
       if (L >= 4 && L <= bv.wn && make_plan(im, L, bv.wn, maxg, p) && p.groups.size() == 1 &&
@@ -385,8 +446,9 @@ int plan_band(const std::vector<InstMeta> &im, uint32_t block, uint32_t grid, ui
       }
     }
   }
-  why = grid ? "no banded kernel gives the requested number of blocks in one launch"
-             : "the network needs more windows than one co-resident launch of the banded engine holds";
+  why = each_L ? "no banded kernel holds the per-instance window lengths in one launch"
+       : grid   ? "no banded kernel gives the requested number of blocks in one launch"
+                : "the network needs more windows than one co-resident launch of the banded engine holds";
   return SNN_E_RANGE;
 }
 
@@ -564,6 +626,17 @@ int snn_build(const snn_config *cfg, snn_net **out) {
     return fail(nullptr, SNN_E_INVAL, "the deviation format runs on the LDS engine only");
   if (cfg->engine > SNN_ENGINE_BAND)
     return fail(nullptr, SNN_E_INVAL, "unknown engine %u", cfg->engine);
+  if (cfg->inst_window_neurons) {
+    if (cfg->window_neurons)
+      return fail(nullptr, SNN_E_INVAL, "window_neurons and per-instance window lengths are exclusive");
+    if (cfg->engine != SNN_ENGINE_LDS && cfg->engine != SNN_ENGINE_BAND)
+      return fail(nullptr, SNN_E_INVAL, "per-instance window lengths need the LDS or banded engine");
+    for (uint32_t k = 0; k < cfg->n_instances; ++k) {
+      const uint32_t L = cfg->inst_window_neurons[k];
+      if (L < 4 || L % 4)
+        return fail(nullptr, SNN_E_INVAL, "instance %u: window length %u (a positive multiple of 4)", k, L);
+    }
+  }
   const auto t_start = std::chrono::steady_clock::now();
 
   snn_net *h = new snn_net();
@@ -573,6 +646,7 @@ int snn_build(const snn_config *cfg, snn_net **out) {
     return fail(nullptr, SNN_E_HIP, "no current HIP device");
   }
   h->cfg.inst = nullptr;
+  h->cfg.inst_window_neurons = nullptr;
   h->chunk = cfg->chunk_steps ? cfg->chunk_steps : 100;
   auto bail = [&](int rc) {
     g_build_error = h->err;
@@ -621,10 +695,10 @@ int snn_build(const snn_config *cfg, snn_net **out) {
       why = b;
     } else if (h->engine == SNN_ENGINE_LDS) {
       prc = plan_lds(h->im, cfg->block_size, cfg->grid_blocks, cfg->window_neurons,
-                     cfg->engine == SNN_ENGINE_LDS, plan, why);
+                     cfg->inst_window_neurons, cfg->engine == SNN_ENGINE_LDS, plan, why);
     } else {
-      prc = plan_band(h->im, cfg->block_size, cfg->grid_blocks, cfg->window_neurons, plan,
-                      h->band_variant, why);
+      prc = plan_band(h->im, cfg->block_size, cfg->grid_blocks, cfg->window_neurons,
+                      cfg->inst_window_neurons, plan, h->band_variant, why);
     }
     if (prc == SNN_OK) {
       lds_window = plan.wn;
@@ -1305,6 +1379,7 @@ namespace {
 
 struct TuneCand {
   uint32_t engine, L;
+  std::vector<uint32_t> each;   // per-instance window lengths (L = 0), or empty
 };
 
 // Candidate layouts of the LDS engines for a configuration: per engine the
@@ -1319,8 +1394,8 @@ std::vector<TuneCand> tune_candidates(const snn_config *cfg) {
     std::string why;
     uint32_t v = 0;
     const int rc = eng == SNN_ENGINE_LDS
-                       ? plan_lds(im, cfg->block_size, cfg->grid_blocks, 0, false, p, why)
-                       : plan_band(im, cfg->block_size, cfg->grid_blocks, 0, p, v, why);
+                       ? plan_lds(im, cfg->block_size, cfg->grid_blocks, 0, nullptr, false, p, why)
+                       : plan_band(im, cfg->block_size, cfg->grid_blocks, 0, nullptr, p, v, why);
     if (rc) return;
     uint32_t L0 = 0;
     for (uint32_t wq : p.wq) L0 = std::max(L0, 4 * wq);
@@ -1328,11 +1403,11 @@ std::vector<TuneCand> tune_candidates(const snn_config *cfg) {
     for (double f : {1.0, 1.25, 1.6}) {
       const uint32_t L = uint32_t(L0 * f + 3.0) & ~3u;
       const int ok = eng == SNN_ENGINE_LDS
-                         ? plan_lds(im, cfg->block_size, cfg->grid_blocks, L, false, p, why)
-                         : plan_band(im, cfg->block_size, cfg->grid_blocks, L, p, v, why);
+                         ? plan_lds(im, cfg->block_size, cfg->grid_blocks, L, nullptr, false, p, why)
+                         : plan_band(im, cfg->block_size, cfg->grid_blocks, L, nullptr, p, v, why);
       if (ok != SNN_OK || std::find(seen.begin(), seen.end(), p.total) != seen.end()) continue;
       seen.push_back(p.total);
-      out.push_back({eng, L});
+      out.push_back({eng, L, {}});
     }
   };
   if (cfg->engine == SNN_ENGINE_AUTO || cfg->engine == SNN_ENGINE_LDS) family(SNN_ENGINE_LDS);
@@ -1384,9 +1459,11 @@ int snn_build_tuned(const snn_config *cfg, uint32_t trial_steps, const char *cac
   if (!trial_steps) return fail(nullptr, SNN_E_INVAL, "trial_steps must be positive");
   if (!cfg || !cfg->inst || cfg->n_instances < 1 || cfg->n_instances > kMaxInstances)
     return fail(nullptr, SNN_E_INVAL, "bad configuration");
+  const uint32_t ni = cfg->n_instances;
   snn_config c = *cfg;
-  const std::vector<TuneCand> cands =
-      cfg->window_neurons ? std::vector<TuneCand>() : tune_candidates(cfg);
+  std::vector<TuneCand> cands = cfg->window_neurons || cfg->inst_window_neurons
+                                    ? std::vector<TuneCand>()
+                                    : tune_candidates(cfg);
   if (cands.empty()) return snn_build(cfg, out);   // nothing to choose
   int dev = 0;
   hipDeviceProp_t prop;
@@ -1395,20 +1472,35 @@ int snn_build_tuned(const snn_config *cfg, uint32_t trial_steps, const char *cac
   char key[160];
   std::snprintf(key, sizeof key, "%s %016llx", prop.gcnArchName,
                 (unsigned long long)config_digest(cfg));
-  TuneCand best{0, 0};
+  TuneCand best{0, 0, {}};
   double best_us = 0.0, first_us = 0.0;
+  uint32_t n_timed = 0;
   bool cached = false;
   if (cache_path) {   // last matching line wins
     if (FILE *f = std::fopen(cache_path, "r")) {
-      char line[256], arch[96], dig[32];
+      std::vector<char> line(16384);
+      char arch[96], dig[32];
       unsigned e = 0, L = 0;
       double us = 0.0, us0 = 0.0;
-      while (std::fgets(line, sizeof line, f))
-        if (std::sscanf(line, "%95s %31s %u %u %lf %lf", arch, dig, &e, &L, &us, &us0) == 6 &&
+      int used = 0;
+      while (std::fgets(line.data(), int(line.size()), f))
+        if (std::sscanf(line.data(), "%95s %31s %u %u %lf %lf%n", arch, dig, &e, &L, &us, &us0,
+                        &used) == 6 &&
             std::strlen(key) == std::strlen(arch) + 1 + std::strlen(dig) &&
             std::strncmp(key, arch, std::strlen(arch)) == 0 &&
             std::strcmp(key + std::strlen(arch) + 1, dig) == 0) {
-          best = {e, L};
+          // An optional seventh field: the per-instance window lengths.
+          std::vector<uint32_t> each;
+          const char *q = line.data() + used;
+          while (*q == ' ') ++q;
+          while (*q >= '0' && *q <= '9') {
+            char *end = nullptr;
+            each.push_back(uint32_t(std::strtoul(q, &end, 10)));
+            q = end;
+            if (*q == ',') ++q;
+          }
+          if (!each.empty() && each.size() != ni) continue;   // not this configuration's
+          best = {e, each.empty() ? L : 0u, each};
           best_us = us;
           first_us = us0;
           cached = true;
@@ -1417,42 +1509,103 @@ int snn_build_tuned(const snn_config *cfg, uint32_t trial_steps, const char *cac
     }
   }
   if (!cached) {
-    for (size_t i = 0; i < cands.size(); ++i) {
-      c.engine = cands[i].engine;
-      c.window_neurons = cands[i].L;
+    // Times one candidate; on the first, also measures the synaptic events
+    // per neuron and step of every instance (the same for every layout).
+    std::vector<double> load;
+    auto time_cand = [&](const TuneCand &cd, bool measure, double &us) -> int {
+      c.engine = cd.engine;
+      c.window_neurons = cd.L;
+      c.inst_window_neurons = cd.each.empty() ? nullptr : cd.each.data();
       snn_net *h = nullptr;
       int rc = snn_build(&c, &h);
       if (rc) return rc;
+      std::vector<uint64_t> e0(ni, 0);
+      auto events = [&](std::vector<uint64_t> &ev) {
+        for (uint32_t k = 0; k < ni && rc == SNN_OK; ++k) {
+          snn_state st{};
+          rc = snn_read_state(h, k, &st);
+          ev[k] = st.events;
+        }
+      };
       double ms = 0.0;
       rc = snn_step_n(h, std::max(1u, trial_steps / 4));
+      if (!rc && measure) events(e0);
       if (!rc) rc = snn_time_steps(h, trial_steps, &ms);
+      if (!rc && measure) {
+        std::vector<uint64_t> e1(ni, 0);
+        events(e1);
+        load.assign(ni, 0.0);
+        for (uint32_t k = 0; k < ni; ++k)
+          load[k] = double(e1[k] - e0[k]) / (double(h->im[k].n) * trial_steps);
+      }
       if (rc) {
         g_build_error = h->err;
         snn_destroy(h);
         return rc;
       }
       snn_destroy(h);
-      const double us = 1000.0 * ms / trial_steps;
-      if (i == 0) first_us = us;
-      if (i == 0 || us < best_us) {
+      us = 1000.0 * ms / trial_steps;
+      ++n_timed;
+      return SNN_OK;
+    };
+    auto consider = [&](const TuneCand &cd, bool first) -> int {
+      double us = 0.0;
+      const int rc = time_cand(cd, first, us);
+      if (rc) return rc;
+      if (first) first_us = us;
+      if (first || us < best_us) {
         best_us = us;
-        best = cands[i];
+        best = cd;
+      }
+      return SNN_OK;
+    };
+    for (size_t i = 0; i < cands.size(); ++i)
+      if (int rc = consider(cands[i], i == 0)) return rc;
+    // Several instances: the winner's kernel and number of blocks again,
+    // with each instance's windows sized by its measured load.
+    double lmax = 0.0;
+    for (double x : load) lmax = std::max(lmax, x);
+    if (ni > 1 && lmax > 0.0) {
+      std::vector<InstMeta> im(ni);
+      for (uint32_t k = 0; k < ni; ++k) im[k].n = instance_neurons(cfg->inst[k]);
+      LdsPlan p;
+      std::string why;
+      uint32_t v = 0, wn = 0;
+      if (best.engine == SNN_ENGINE_LDS) {
+        if (plan_lds(im, cfg->block_size, cfg->grid_blocks, best.L, nullptr, false, p, why) == SNN_OK)
+          wn = p.wn;
+      } else if (plan_band(im, cfg->block_size, cfg->grid_blocks, best.L, nullptr, p, v, why) == SNN_OK) {
+        wn = kBandVariants[v].wn;
+      }
+      std::vector<uint32_t> Ls;
+      if (wn && balanced_lengths(im, load, wn, p.total, Ls)) {
+        const int ok = best.engine == SNN_ENGINE_LDS
+                           ? plan_lds(im, cfg->block_size, cfg->grid_blocks, 0, Ls.data(), false, p, why)
+                           : plan_band(im, cfg->block_size, cfg->grid_blocks, 0, Ls.data(), p, v, why);
+        if (ok == SNN_OK) {
+          cands.push_back({best.engine, 0u, Ls});
+          if (int rc = consider(cands.back(), false)) return rc;
+        }
       }
     }
     if (cache_path) {
       if (FILE *f = std::fopen(cache_path, "a")) {
-        std::fprintf(f, "%s %u %u %.4f %.4f\n", key, best.engine, best.L, best_us, first_us);
+        std::fprintf(f, "%s %u %u %.4f %.4f", key, best.engine, best.L, best_us, first_us);
+        for (size_t k = 0; k < best.each.size(); ++k)
+          std::fprintf(f, "%c%u", k ? ',' : ' ', best.each[k]);
+        std::fprintf(f, "\n");
         std::fclose(f);
       }
     }
   }
   c.engine = best.engine;
   c.window_neurons = best.L;
+  c.inst_window_neurons = best.each.empty() ? nullptr : best.each.data();
   const int rc = snn_build(&c, out);
   if (rc) return rc;
   const snn_net *h = *out;
   rep->engine = h->engine;
-  rep->candidates = cached ? 0u : uint32_t(cands.size());
+  rep->candidates = cached ? 0u : n_timed;
   rep->block_size = h->shape.block;
   rep->grid_blocks = h->shape.grid;
   rep->quads_per_thread = h->shape.qpt;

@@ -23,7 +23,7 @@ ENGINE_STEPWISE = 1
 ENGINE_PERSISTENT = 2
 ENGINE_LDS = 3
 ENGINE_BAND = 4
-ABI_VERSION = 3
+ABI_VERSION = 4
 
 SNN_OK = 0
 ERRORS = {-1: "SNN_E_INVAL", -2: "SNN_E_NOMEM", -3: "SNN_E_HIP", -4: "SNN_E_RANGE",
@@ -54,7 +54,7 @@ class _Cfg(C.Structure):
                 ("grid_blocks", C.c_uint32), ("raster_capacity", C.c_uint64),
                 ("host_threads", C.c_int32), ("use_graphs", C.c_int32),
                 ("window_neurons", C.c_uint32), ("reserved0", C.c_uint32),
-                ("hip_stream", C.c_void_p), ("dev_alloc", _ALLOC), ("dev_free", _FREE),
+                ("inst_window_neurons", C.POINTER(C.c_uint32)), ("hip_stream", C.c_void_p), ("dev_alloc", _ALLOC), ("dev_free", _FREE),
                 ("alloc_ctx", C.c_void_p)]
 
 
@@ -196,10 +196,13 @@ class Simulator:
 
     def __init__(self, instances, syn_format="plain", engine="auto", chunk_steps=100,
                  use_graphs=True, block_size=0, grid_blocks=0, raster_capacity=0,
-                 host_threads=0, device=0, window_neurons=0, tune_steps=0, tune_cache=None):
+                 host_threads=0, device=0, window_neurons=0, tune_steps=0, tune_cache=None,
+                 inst_window_neurons=None):
         """tune_steps > 0 builds through snn_build_tuned (the LDS engines' layout
         chosen by timing that many steps per candidate; tune_cache: a file of
-        earlier choices); the report is kept in self.tune_report."""
+        earlier choices); the report is kept in self.tune_report.
+        inst_window_neurons: one window length per instance (LDS or banded
+        engine), in place of window_neurons."""
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("no GPU: the simulator runs only on an MI355X (gfx950)")
@@ -242,6 +245,10 @@ class Simulator:
         cfg.raster_capacity = int(raster_capacity)
         cfg.host_threads = int(host_threads)
         cfg.window_neurons = int(window_neurons)
+        if inst_window_neurons is not None:
+            each = (C.c_uint32 * len(self.instances))(*[int(x) for x in inst_window_neurons])
+            keep.append(each)
+            cfg.inst_window_neurons = C.cast(each, C.POINTER(C.c_uint32))
         cfg.hip_stream = C.c_void_p(self.stream.cuda_stream)
         cfg.dev_alloc = self._alloc_cb
         cfg.dev_free = self._free_cb

@@ -359,6 +359,80 @@ def test_tuned_build_bit_exact_and_cached(P, oracle, tmp_path):
         assert_parity(sim, 0, net, osim)
 
 
+def _windows(n, L):
+    """Windows of an instance of n neurons at window length L (the plan's
+    rule: balanced windows of whole quads)."""
+    nq = (n + 3) // 4
+    nw = -(-nq // (L // 4))
+    wq = -(-nq // nw)
+    return -(-nq // wq)
+
+
+UNEVEN = [dict(scale=0.01, seed=11), dict(scale=0.023, seed=12, g=-5.0, bg_rate_hz=9.0),
+          dict(scale=0.013, seed=13, g=-3.5, bg_rate_hz=6.5, indegree_mode=1),
+          dict(scale=0.002, seed=14)]
+
+
+@pytest.mark.parametrize("engine,block,each", [("band", 256, [128, 256, 64, 40]),
+                                               ("band", 1024, [600, 96, 1500, 4]),
+                                               ("lds", 256, [200, 120, 320, 44])])
+def test_per_instance_windows_bit_exact(P, oracle, engine, block, each):
+    """One window length per instance (windows sized by load, Sec. 3.6's
+    destination classes): the plan cuts each instance at its own length, and
+    every instance still matches its own oracle run."""
+    insts = [P.Instance(**kw) for kw in UNEVEN]
+    for fmt, wmode in [("plain", 0), ("compressed", 1)]:
+        say("per-instance windows", engine, block, each, fmt)
+        with P.Simulator(insts, syn_format=fmt, engine=engine, block_size=block, chunk_steps=70,
+                         inst_window_neurons=each) as sim:
+            info = sim.info()
+            say("per-instance windows info", info)
+            n = [len(sim.state(k)["U"]) for k in range(len(insts))]
+            assert info["grid_blocks"] == sum(_windows(nk, L) for nk, L in zip(n, each))
+            assert info["window_neurons"] <= max(each)
+            sim.step(300)
+            for k, inst in enumerate(insts):
+                net, osim = run_oracle(oracle, inst, wmode, 300)
+                assert_parity(sim, k, net, osim)
+
+
+def test_tuned_build_balances_instances(P, oracle, tmp_path):
+    """With several instances the tuner also times the winning kernel with
+    windows sized by each instance's measured events; the cache keeps
+    per-instance lengths and a cached line with them rebuilds that layout."""
+    insts = [P.Instance(scale=0.02, seed=51, g=-3.0, bg_rate_hz=10.0),
+             P.Instance(scale=0.03, seed=52, g=-6.0, bg_rate_hz=6.0),
+             P.Instance(scale=0.01, seed=53)]
+    cache = str(tmp_path / "tune.txt")
+    with P.Simulator(insts, engine="band", chunk_steps=100, tune_steps=400, tune_cache=cache) as sim:
+        rep = sim.tune_report
+        say("tuned batch", rep, sim.info())
+        assert rep["candidates"] >= 2 and rep["us_per_step_best"] <= rep["us_per_step_first"]
+        n = [len(sim.state(k)["U"]) for k in range(len(insts))]
+        sim.step(200)
+        for k, inst in enumerate(insts):
+            net, osim = run_oracle(oracle, inst, 0, 200)
+            assert_parity(sim, k, net, osim)
+    line = open(cache).read().split()
+    assert len(line) in (6, 7)
+    # A hand-written per-instance choice for the same key is taken from the
+    # cache (the last matching line wins).
+    each = [64, 512, 128]
+    with open(cache, "a") as f:
+        f.write(" ".join(line[:2] + [str(P.ENGINE_BAND), "0", "1.0", "1.0",
+                                     ",".join(map(str, each))]) + "\n")
+    with P.Simulator(insts, engine="band", chunk_steps=100, tune_steps=400, tune_cache=cache) as sim:
+        rep2 = sim.tune_report
+        info = sim.info()
+        say("cached per-instance layout", rep2, info)
+        assert rep2["candidates"] == 0 and info["engine"] == P.ENGINE_BAND
+        assert info["grid_blocks"] == sum(_windows(nk, L) for nk, L in zip(n, each))
+        sim.step(200)
+        for k, inst in enumerate(insts):
+            net, osim = run_oracle(oracle, inst, 0, 200)
+            assert_parity(sim, k, net, osim)
+
+
 @pytest.fixture(scope="module")
 def full_oracle(oracle):
     """Oracle run of the full-scale microcircuit, 300 steps."""

@@ -1,11 +1,13 @@
-"""Parity at the benchmark's own workloads, on the engine and launch length
-the benchmark uses (the automatic engine choice, 10,000-step chunks, after
-the launch-shape tuner has run):
+"""Parity at the benchmark's own workloads, on the layout, engine and launch
+length the benchmark uses (the layout from the committed tuning cache --
+timed anew if the cache has no entry for this GPU --, 10,000-step chunks,
+after the launch-shape tuner has run):
 
 * the batch of 64 independent instances of uneven scale (5-20 %), g,
   background rate and seed (576,807 neurons, 2.2e9 synapses): every
   instance equals its own oracle run spike for spike, with its state (the
-  banded engine's 1,024-thread variant, 8 ring rows);
+  banded engine's 1,024-thread variant, 8 ring rows, windows sized per
+  instance by its measured load);
 * the 4x circuit with full-scale in-degrees (308,676 neurons, 1.2e9
   synapses), whose 64-row ring exceeds the chip's LDS: the banded engine
   (Sec. 3.4's horizon with 16 ring rows) against the oracle.
@@ -14,6 +16,7 @@ Both networks hold more than 2^31 record slots, so these are also the
 regression tests of 64-bit record addressing.  Each case builds the oracle
 network of the same configuration on the host (about 40 GB for the 4x
 circuit)."""
+import os
 import sys
 
 import numpy as np
@@ -22,6 +25,9 @@ import pytest
 from test_gpu_parity import assert_parity, run_oracle
 
 pytestmark = pytest.mark.gpu
+
+CACHE = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                     "paper_2405_02019_amd", "tune_cache.txt")
 
 
 def say(*a):
@@ -59,9 +65,10 @@ def test_batch_of_64_bit_exact(P, oracle, fmt, wmode):
     from paper_2405_02019_amd import workloads
     insts = workloads.batch()
     say("batch", fmt, "building")
-    with P.Simulator(insts, syn_format=fmt, chunk_steps=10000) as sim:
+    with P.Simulator(insts, syn_format=fmt, chunk_steps=10000, tune_steps=2000,
+                     tune_cache=CACHE) as sim:
         info = sim.info()
-        say("batch info", info)
+        say("batch info", info, sim.tune_report)
         assert info["engine"] == P.ENGINE_BAND
         rep = sim.autotune(50)
         say("batch autotune", rep)
@@ -84,9 +91,10 @@ def test_x4_circuit_bit_exact(P, oracle, fmt, wmode):
     from paper_2405_02019_amd import workloads
     inst = workloads.stress_x4()[0]
     say("x4", fmt, "building")
-    with P.Simulator(inst, syn_format=fmt, chunk_steps=10000) as sim:
+    with P.Simulator(inst, syn_format=fmt, chunk_steps=10000, tune_steps=2000,
+                     tune_cache=CACHE) as sim:
         info = sim.info()
-        say("x4 info", info)
+        say("x4 info", info, sim.tune_report)
         assert info["engine"] == P.ENGINE_BAND and info["ring_rows"] < 64
         rep = sim.autotune(40)
         total = rep["candidates"] * 40 + 160

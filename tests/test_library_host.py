@@ -91,6 +91,38 @@ def test_build_rejects_bad_configs_without_gpu(P):
     L.snn_destroy(None)
 
 
+def test_per_instance_windows_are_checked_without_gpu(P):
+    """Per-instance window lengths (load-balanced windows, Sec. 3.6's
+    destination classes sized by their events): positive multiples of 4, for
+    the LDS or banded engine, exclusive with window_neurons; all three are
+    refused before any device call."""
+    S = P.snn
+    L = P.lib()
+    h = C.c_void_p()
+    insts = (S._Inst * 2)()
+    for k in range(2):
+        L.snn_instance_default(C.byref(insts[k]))
+    cfg = S._Cfg()
+    L.snn_config_default(C.byref(cfg))
+    cfg.n_instances = 2
+    cfg.inst = C.cast(insts, C.POINTER(S._Inst))
+    each = (C.c_uint32 * 2)(256, 512)
+    cfg.inst_window_neurons = C.cast(each, C.POINTER(C.c_uint32))
+    cfg.engine = P.ENGINE_BAND
+    cfg.window_neurons = 256
+    assert L.snn_build(C.byref(cfg), C.byref(h)) == -1
+    assert b"exclusive" in L.snn_last_error(None)
+    cfg.window_neurons = 0
+    cfg.engine = 0   # automatic choice
+    assert L.snn_build(C.byref(cfg), C.byref(h)) == -1
+    assert b"LDS or banded" in L.snn_last_error(None)
+    cfg.engine = P.ENGINE_LDS
+    each[1] = 258
+    assert L.snn_build(C.byref(cfg), C.byref(h)) == -1
+    assert b"instance 1: window length 258" in L.snn_last_error(None)
+    assert not h
+
+
 @pytest.mark.parametrize("fmt,wmode", [("plain", 0), ("compressed", 1)])
 @pytest.mark.parametrize("scale,mode,seed", [(0.01, 0, 1), (0.05, 0, 9), (0.04, 1, 4)])
 def test_sampler_equals_oracle(P, oracle, fmt, wmode, scale, mode, seed):
