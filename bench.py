@@ -49,8 +49,9 @@ WORKLOADS = {
 }
 # Sources whose bytes (concatenated in this order) a committed counter record
 # must match: the kernel's file and the device helpers it includes.
-KERNEL_SOURCES = {"k_lds": ["kernels.hip", "device.hpp"], "k_persistent": ["kernels.hip", "device.hpp"],
-                  "k_band": ["band.hip", "device.hpp"]}
+KERNEL_SOURCES = {"k_lds": ["kernels.hip", "device.hpp", "engine.hpp"],
+                  "k_persistent": ["kernels.hip", "device.hpp"],
+                  "k_band": ["band.hip", "device.hpp", "engine.hpp"]}
 
 
 def algorithmic_bytes(n_neurons, spikes, events, rec_bytes):
