@@ -73,3 +73,24 @@ def test_noalloc_matches_step_n():
     for a, b, _ in sims:
         a.close()
         b.close()
+
+
+def test_noalloc_burst_reaches_every_sender_history_tier():
+    """The banded engine's 512-thread variant under a burst (half-scale
+    circuit, g = -2, 16 Hz background): steps of more than 320 senders fill
+    the LDS history (128 ids per step), the block's private history (192
+    more) and the shared one, all three carved from the static scratch area
+    by the allocation-free call; it equals snn_step_n bit for bit."""
+    import torch
+    import paper_2405_02019_amd as P
+    inst = P.Instance(scale=0.5, seed=7, g=-2.0, bg_rate_hz=16.0)
+    say("burst case, band 512")
+    a = P.Simulator(inst, syn_format="compressed", engine="band", block_size=512, chunk_steps=60)
+    b = P.Simulator(inst, syn_format="compressed", engine="band", block_size=512, chunk_steps=60)
+    assert a.info()["ring_rows"] == 16
+    steps, ids = gpu_raster(torch, a, 150)
+    b.step(150)
+    compare(a, b, steps, ids, 0, 150)
+    assert np.bincount(steps, minlength=150).max() > 320
+    a.close()
+    b.close()
