@@ -120,7 +120,11 @@ typedef struct {
                                   0 = 100                                         */
   uint32_t block_size;         /* threads per block; 0 = tuned                   */
   uint32_t grid_blocks;        /* blocks of the persistent kernel; 0 = tuned     */
-  uint64_t raster_capacity;    /* device raster entries between drains; 0 = auto */
+  uint64_t raster_capacity;    /* device raster entries between drains; 0 = auto;
+                                  two buffers of it (one for the graph-replayed
+                                  stepwise engine): the step loop swaps them at
+                                  a drain and reads the full one back while the
+                                  next chunk runs                                */
   int32_t host_threads;        /* threads of the network sampler; 0 = auto       */
   int32_t use_graphs;          /* 1: replay chunks from a captured HIP graph     */
   uint32_t window_neurons;     /* LDS engines: neurons per window (a multiple of

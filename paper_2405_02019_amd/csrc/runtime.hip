@@ -44,6 +44,9 @@ struct snn_net {
   hipGraphExec_t graph_exec = nullptr;
   std::vector<uint64_t> raster;     // drained; sorted by (step, global id) up to raster_sorted
   uint64_t *staging = nullptr;      // pinned host buffer for raster drains
+  uint64_t *raster_alt = nullptr;   // second device raster (engines without a captured graph):
+                                    // the step loop swaps to it at a drain and reads the
+                                    // other back while the next chunk runs
   size_t staging_cap = 0;           // its capacity in entries
   size_t raster_sorted = 0;         // later drains hold later steps: only the tail needs sorting
   uint64_t raster_version = 0;      // bumped whenever the stored raster changes
@@ -124,8 +127,30 @@ void release(snn_net *h) {
   h->stream = nullptr;
 }
 
-// Copy the device raster to the host store and reset it.
-int drain(snn_net *h) {
+// Appends m entries of a device raster buffer to the host store, through a
+// pinned buffer (a copy into pageable memory is staged by the runtime in
+// small pieces).  The buffer grows to twice what is needed: freeing pinned
+// memory waits for the device, which would leave it idle until the next
+// chunk is queued.
+int store_raster(snn_net *h, const uint64_t *src, uint64_t m) {
+  if (m > h->staging_cap) {
+    if (h->staging) (void)hipHostFree(h->staging);
+    h->staging = nullptr;
+    h->staging_cap = 0;
+    const size_t cap = std::max<size_t>(2 * m, size_t(1) << 21);
+    HIP_OK(h, hipHostMalloc(reinterpret_cast<void **>(&h->staging), cap * sizeof(uint64_t),
+                            hipHostMallocDefault));
+    h->staging_cap = cap;
+  }
+  HIP_OK(h, hipMemcpy(h->staging, src, m * sizeof(uint64_t), hipMemcpyDeviceToHost));
+  h->raster.insert(h->raster.end(), h->staging, h->staging + m);
+  ++h->raster_version;
+  return SNN_OK;
+}
+
+// Waits for the queued steps and reads the control words: the entries in
+// the device raster (*m), a device error, an overflow.
+int settle(snn_net *h, uint64_t *m, bool *reset) {
   HIP_OK(h, hipStreamSynchronize(h->stream));
   Control c{};
   HIP_OK(h, hipMemcpy(&c, h->d.ctl, sizeof c, hipMemcpyDeviceToHost));
@@ -134,24 +159,32 @@ int drain(snn_net *h) {
     return fail(h, SNN_E_DEVICE, "a bounded device wait expired (code %u)", c.error);
   }
   if (c.overflow) h->overflowed = true;
-  const uint64_t m = std::min<uint64_t>(c.raster_n, h->d.raster_cap);
+  *m = std::min<uint64_t>(c.raster_n, h->d.raster_cap);
+  *reset = c.raster_n || c.overflow;
+  return SNN_OK;
+}
+
+// Copy the device raster to the host store and reset it.
+int drain(snn_net *h) {
+  uint64_t m = 0;
+  bool reset = false;
+  if (int rc = settle(h, &m, &reset)) return rc;
   if (m) {
-    // Through a pinned buffer: a copy into pageable memory is staged by the
-    // runtime in small pieces.
-    if (m > h->staging_cap) {
-      if (h->staging) (void)hipHostFree(h->staging);
-      h->staging = nullptr;
-      h->staging_cap = 0;
-      const size_t cap = std::max<size_t>(m, size_t(1) << 18);
-      HIP_OK(h, hipHostMalloc(reinterpret_cast<void **>(&h->staging), cap * sizeof(uint64_t),
-                              hipHostMallocDefault));
-      h->staging_cap = cap;
-    }
-    HIP_OK(h, hipMemcpy(h->staging, h->d.raster, m * sizeof(uint64_t), hipMemcpyDeviceToHost));
-    h->raster.insert(h->raster.end(), h->staging, h->staging + m);
-    ++h->raster_version;
+    if (int rc = store_raster(h, h->d.raster, m)) return rc;
   }
-  if (c.raster_n || c.overflow) HIP_OK(h, launch_reset_raster(h->d, h->stream));
+  if (reset) HIP_OK(h, launch_reset_raster(h->d, h->stream));
+  h->pending = 0;
+  return SNN_OK;
+}
+
+// The step loop's drain: the next steps write into the other raster buffer,
+// so they can be queued before the full one (*old, *m entries) is read back.
+int swap_raster(snn_net *h, const uint64_t **old, uint64_t *m) {
+  bool reset = false;
+  if (int rc = settle(h, m, &reset)) return rc;
+  *old = h->d.raster;
+  std::swap(h->d.raster, h->raster_alt);
+  if (reset) HIP_OK(h, launch_reset_raster(h->d, h->stream));
   h->pending = 0;
   return SNN_OK;
 }
@@ -833,6 +866,8 @@ int snn_build(const snn_config *cfg, snn_net **out) {
   }
   ALLOC(d.spk_list, 2 * size_t(d.ntot));
   ALLOC(d.raster, cap);
+  // A captured graph holds the raster's address: only the other engines swap.
+  if (!(cfg->use_graphs && h->engine == SNN_ENGINE_STEPWISE)) ALLOC(h->raster_alt, cap);
   ALLOC(d.wave_ctr, 4 * size_t(d.nquads / 64));
   ALLOC(d.events, ni);
   ALLOC(d.consts, 1);
@@ -1065,11 +1100,19 @@ int snn_step_n(snn_net *h, uint64_t n_steps) {
   while (n_steps) {
     uint64_t piece = std::min<uint64_t>(n_steps, h->chunk);
     while (piece > 1 && spike_bound(h, piece) > h->d.raster_cap) piece /= 2;
+    const uint64_t *old = nullptr;
+    uint64_t m_old = 0;
     if (h->pending + spike_bound(h, piece) > h->d.raster_cap) {
-      int rc = drain(h);
+      int rc = h->raster_alt ? swap_raster(h, &old, &m_old) : drain(h);
       if (rc) return rc;
     }
     int rc = queue_steps(h, uint32_t(piece));
+    // The full buffer is read back while the device runs the chunk just
+    // queued (it is not written again before the next drain).
+    if (m_old) {
+      const int rs = store_raster(h, old, m_old);
+      if (!rc) rc = rs;
+    }
     if (rc) return rc;
     h->pending += spike_bound(h, piece);
     h->t += piece;
