@@ -58,13 +58,17 @@ enum snn_syn_format {
      then target block (the 16-bit weights of Sec. 5.3).  The LDS engines
      pack the same weight, delay and window offset into one 4-byte record. */
   SNN_SYN_COMPRESSED5 = 1,
-  /* 3 bytes in two streams, LDS engine only: a uint16 locator (bit 15: the
-     doubled L4e -> L2/3e pair; bits 9-14: delay; bits 0-8: target offset in
-     a window of at most 512 neurons) and an int8 deviation of the weight from
-     the mean of its population pair, in steps of 5 sd / 127 of that pair;
-     the weight is mean + deviation * step in 2^-8 pA, both rounded to that
-     unit (Sec. 5.3: the weights are drawn from Gaussians of known mean, so
-     their deviations from the mean need fewer bits). */
+  /* 3 bytes in two streams, LDS and banded engines only: a uint16 locator
+     and an int8 deviation of the weight from the mean of its population
+     pair, in steps of 5 sd / 127 of that pair; the weight is mean +
+     deviation * step in 2^-8 pA, both rounded to that unit (Sec. 5.3: the
+     weights are drawn from Gaussians of known mean, so their deviations from
+     the mean need fewer bits).  LDS engine locator: bit 15 the doubled
+     L4e -> L2/3e pair, bits 9-14 the delay, bits 0-8 the target offset in a
+     window of at most 512 neurons.  Banded engine locator (H ring rows):
+     bit 15 the doubled pair, then the delay minus its band's first delay in
+     log2(H) bits, then the target offset in 15 - log2(H) bits; deviation
+     -128 marks an unused slot. */
   SNN_SYN_DEV8 = 2
 };
 

@@ -83,16 +83,31 @@ __device__ __forceinline__ uint32_t band_sender_gid(const uint32_t *llist, uint3
   return w0 + ld_ag(llist + size_t(lslot) * ntot + w0 + kk);
 }
 
+// Record formats of the banded layout: plain (8 bytes), compressed (4
+// bytes), deviation (a 2-byte locator and a 1-byte deviation from the mean
+// of the sender's population pair).
+constexpr int kBandPlain = 0, kBandComp = 1, kBandDev = 2;
+
 // Decoded record: the weight (0 for an unused slot), the row it adds to
-// (absolute step, low 32 bits) and its offset in the window.
-template <bool COMP, int H>
-__device__ __forceinline__ void decode(uint64_t rec8, uint32_t rec4, uint32_t rb, uint32_t wb0,
-                                       int32_t &w, uint32_t &row, uint32_t &loc) {
-  if (COMP) {
+// (absolute step, low 32 bits) and its offset in the window.  Deviation
+// format: loc2 the locator, dv the deviation, pc the sender's population, dq
+// and dsq the mean and step of each (population, doubled) pair.
+template <int FMT, int H>
+__device__ __forceinline__ void decode(uint64_t rec8, uint32_t rec4, uint32_t loc2, int32_t dv,
+                                       uint32_t pc, const int32_t *dq, const int32_t *dsq,
+                                       uint32_t rb, uint32_t wb0, int32_t &w, uint32_t &row,
+                                       uint32_t &loc) {
+  if (FMT == kBandComp) {
     constexpr uint32_t OB = band_offset_bits(H);
     w = int32_t(int16_t(uint16_t(rec4 >> 16))) * 8;
     row = rb + ((rec4 & 0xFFFFu) >> OB);
     loc = rec4 & ((1u << OB) - 1u);
+  } else if (FMT == kBandDev) {
+    constexpr uint32_t OD = band_dev_offset_bits(H);
+    const uint32_t di = 2u * pc + (loc2 >> 15);
+    w = dv == -128 ? 0 : dq[di] + dv * dsq[di];
+    row = rb + ((loc2 >> OD) & uint32_t(H - 1));
+    loc = loc2 & ((1u << OD) - 1u);
   } else {
     const uint32_t hiw = uint32_t(rec8 >> 32);
     w = int32_t(uint32_t(rec8));
@@ -120,13 +135,16 @@ __device__ __forceinline__ void decode(uint64_t rec8, uint32_t rec4, uint32_t rb
 // measured to pay (the 512-thread variant with 16 ring rows, whose slow bands
 // otherwise take several rounds of loads; elsewhere the other two fit one
 // round and are faster).  UR loads are in flight per lane.
-template <bool COMP, int UR, int H, bool PACK>
+template <int FMT, int UR, int H, bool PACK>
 struct BandWalk {
-  uint64_t rec[COMP ? 1 : UR];
-  uint32_t r4[COMP ? UR : 1];
+  uint64_t rec[FMT == kBandPlain ? UR : 1];
+  uint32_t r4[FMT == kBandComp ? UR : 1];
+  uint32_t r2[FMT == kBandDev ? UR : 1];    // deviation format: locator
+  int32_t dv[FMT == kBandDev ? UR : 1];     // and deviation (-128: unused slot)
+  uint32_t pcv[FMT == kBandDev ? UR : 1];   // and the sender's population
   uint32_t rbv[UR];
   uint64_t base_l;
-  uint32_t cap_l, rb_l;
+  uint32_t cap_l, rb_l, cls_l;
   uint32_t G;        // lanes per sender (grouped), or 64 with pieces
   uint32_t mode;     // 0 grouped, 1 pieces, 2 packed (wave-uniform)
   uint32_t p_l;      // pieces: the lane's first piece; packed: its first slot
@@ -135,11 +153,13 @@ struct BandWalk {
   uint32_t u0;       // next unit
   uint32_t nv;       // slots filled by the last load()
 
+  // cls: the lane's sender population (read by the deviation format only).
   __device__ __forceinline__ void begin(uint64_t base, uint32_t cap, uint32_t rb, uint32_t nsend,
-                                        uint32_t gmax) {
+                                        uint32_t gmax, uint32_t cls) {
     base_l = base;
     cap_l = cap;
     rb_l = rb;
+    cls_l = cls;
     u0 = 0;
     total = 0;
     if (PACK) {
@@ -161,6 +181,27 @@ struct BandWalk {
   }
   __device__ __forceinline__ bool more() const { return u0 < nu; }
 
+  // Slot u holds nothing (decodes to weight 0).
+  __device__ __forceinline__ void clear(int u) {
+    if (FMT == kBandComp) r4[u] = 0u;
+    if (FMT == kBandPlain) rec[u] = 0ull;
+    if (FMT == kBandDev) {
+      r2[u] = 0u;
+      dv[u] = -128;
+      pcv[u] = 0u;
+    }
+  }
+  // Loads slot u from record address addr when ok.
+  __device__ __forceinline__ void fetch(const DeviceNet &d, int u, uint64_t addr, bool ok) {
+    if (!ok) return;
+    if (FMT == kBandComp) r4[u] = __builtin_nontemporal_load(d.rec4 + addr);
+    if (FMT == kBandPlain) rec[u] = __builtin_nontemporal_load(d.rec8 + addr);
+    if (FMT == kBandDev) {
+      r2[u] = uint32_t(__builtin_nontemporal_load(d.rec2 + addr));
+      dv[u] = int32_t(__builtin_nontemporal_load(d.dev8 + addr));
+    }
+  }
+
   __device__ __forceinline__ void load(const DeviceNet &d) {
     if constexpr (PACK) {
       load_packed(d);
@@ -170,7 +211,7 @@ struct BandWalk {
 #pragma unroll
     for (int u = 0; u < UR; ++u) {
       const uint32_t U = u0 + uint32_t(u);
-      if (COMP) r4[u] = 0u; else rec[u] = 0ull;
+      clear(u);
       rbv[u] = 0;
       if (U >= nu) continue;   // wave-uniform
       uint64_t addr;
@@ -183,6 +224,7 @@ struct BandWalk {
         const uint32_t bhi = __shfl(uint32_t(base_l >> 32), int(k & 63u));
         uint32_t cap = __shfl(cap_l, int(k & 63u));
         rbv[u] = __shfl(rb_l, int(k & 63u));
+        if (FMT == kBandDev) pcv[u] = __shfl(cls_l, int(k & 63u));
         cap = k < 64u ? cap : 0u;
         addr = join64(bhi, blo) + off;
         ok = off < cap;
@@ -193,6 +235,7 @@ struct BandWalk {
         const uint32_t k = U - __builtin_amdgcn_readlane(p_l, s);
         const uint32_t cap = __builtin_amdgcn_readlane(cap_l, s);
         rbv[u] = __builtin_amdgcn_readlane(rb_l, s);
+        if (FMT == kBandDev) pcv[u] = __builtin_amdgcn_readlane(cls_l, s);
         const uint32_t off = 64u * k + lane;
         addr = join64(uint32_t(__builtin_amdgcn_readlane(uint32_t(base_l >> 32), s)),
                       uint32_t(__builtin_amdgcn_readlane(uint32_t(base_l), s))) + off;
@@ -201,11 +244,7 @@ struct BandWalk {
         addr = 0;
         ok = false;
       }
-      if (COMP) {
-        if (ok) r4[u] = __builtin_nontemporal_load(d.rec4 + addr);
-      } else {
-        if (ok) rec[u] = __builtin_nontemporal_load(d.rec8 + addr);
-      }
+      fetch(d, u, addr, ok);
     }
     nv = min(nu - u0, uint32_t(UR));
     u0 += UR;
@@ -226,7 +265,7 @@ struct BandWalk {
     for (int g = 0; g < UR; g += PG) {
 #pragma unroll
       for (int v = 0; v < PG; ++v) {
-        if (COMP) r4[g + v] = 0u; else rec[g + v] = 0ull;
+        clear(g + v);
         rbv[g + v] = 0;
       }
       if (u0 + uint32_t(g) >= nu) continue;   // wave-uniform
@@ -255,11 +294,9 @@ struct BandWalk {
         const uint32_t blo = __shfl(uint32_t(base_l), int(sv[v]));
         const uint32_t bhi = __shfl(uint32_t(base_l >> 32), int(sv[v]));
         rbv[g + v] = __shfl(rb_l, int(sv[v]));
+        if (FMT == kBandDev) pcv[g + v] = __shfl(cls_l, int(sv[v]));
         const uint64_t addr = join64(bhi, blo) + (slot[v] - ps[v]);
-        if (slot[v] < total) {
-          if (COMP) r4[g + v] = __builtin_nontemporal_load(d.rec4 + addr);
-          else rec[g + v] = __builtin_nontemporal_load(d.rec8 + addr);
-        }
+        fetch(d, g + v, addr, slot[v] < total);
       }
     }
     nv = min(nu - u0, uint32_t(UR));
@@ -268,7 +305,8 @@ struct BandWalk {
 
   // Adds the loaded records into the LDS ring (rows mod H).
   template <int WN>
-  __device__ __forceinline__ void apply(int32_t *s_ring, uint32_t wb0) const {
+  __device__ __forceinline__ void apply(int32_t *s_ring, uint32_t wb0, const int32_t *dq,
+                                        const int32_t *dsq) const {
 #pragma unroll
     for (int u = 0; u < UR; ++u) {
       if (uint32_t(u) >= nv) {   // wave-uniform; past 8 slots the compiler unrolls
@@ -277,7 +315,9 @@ struct BandWalk {
       }
       int32_t w;
       uint32_t row, loc;
-      decode<COMP, H>(COMP ? 0ull : rec[u], COMP ? r4[u] : 0u, rbv[u], wb0, w, row, loc);
+      decode<FMT, H>(FMT == kBandPlain ? rec[u] : 0ull, FMT == kBandComp ? r4[u] : 0u,
+                     FMT == kBandDev ? r2[u] : 0u, FMT == kBandDev ? dv[u] : 0,
+                     FMT == kBandDev ? pcv[u] : 0u, dq, dsq, rbv[u], wb0, w, row, loc);
       if (w) atomicAdd(&s_ring[(row & (H - 1u)) * WN + loc], w);
     }
   }
@@ -287,7 +327,8 @@ struct BandWalk {
   // the block's own window only).
   template <int WN>
   __device__ __forceinline__ void apply_flush(int32_t *s_ring, int32_t *W, uint32_t ntot, uint32_t wb0,
-                                              uint32_t t_end) const {
+                                              uint32_t t_end, const int32_t *dq,
+                                              const int32_t *dsq) const {
 #pragma unroll
     for (int u = 0; u < UR; ++u) {
       if (uint32_t(u) >= nv) {   // wave-uniform; past 8 slots the compiler unrolls
@@ -296,7 +337,9 @@ struct BandWalk {
       }
       int32_t w;
       uint32_t row, loc;
-      decode<COMP, H>(COMP ? 0ull : rec[u], COMP ? r4[u] : 0u, rbv[u], wb0, w, row, loc);
+      decode<FMT, H>(FMT == kBandPlain ? rec[u] : 0ull, FMT == kBandComp ? r4[u] : 0u,
+                     FMT == kBandDev ? r2[u] : 0u, FMT == kBandDev ? dv[u] : 0,
+                     FMT == kBandDev ? pcv[u] : 0u, dq, dsq, rbv[u], wb0, w, row, loc);
       if (!w) continue;
       if (row - t_end < uint32_t(H))
         atomicAdd(&s_ring[(row & (H - 1u)) * WN + loc], w);
@@ -306,7 +349,7 @@ struct BandWalk {
   }
 };
 
-template <int BS, int WN, int H, int HC, bool COMP>
+template <int BS, int WN, int H, int HC, int FMT>
 __global__ __launch_bounds__(BS) void k_band(DeviceNet d, uint32_t n_steps, uint32_t spin_limit) {
   using F = FlagFmt<WN>;
   constexpr uint32_t NW = BS / 64;
@@ -330,6 +373,7 @@ __global__ __launch_bounds__(BS) void k_band(DeviceNet d, uint32_t n_steps, uint
   __shared__ __align__(16) uint32_t s_thr[8 * TS];
   __shared__ uint32_t s_tlen[8];
   __shared__ uint32_t s_cf[8], s_cn[8];        // sender classes: first id, count
+  __shared__ int32_t s_dq[16], s_ds[16];       // deviation format: mean and step per (class, doubled)
   __shared__ uint32_t s_ccap[NB * 8];          // per band and class: slots per sender
   __shared__ uint64_t s_cbase[NB * 8];
   __shared__ uint32_t s_gmax[NB];              // per band: group width (<= 64), or 65
@@ -386,6 +430,10 @@ __global__ __launch_bounds__(BS) void k_band(DeviceNet d, uint32_t n_steps, uint
   }
   if (tid < 4u) s_ctr[tid] = 0;
   if (tid < NSLOT) s_hn[tid] = 0;
+  if (FMT == kBandDev && tid < 16u) {
+    s_dq[tid] = ip->dev_mq[tid];
+    s_ds[tid] = ip->dev_sq[tid];
+  }
   for (uint32_t i = tid; i < rel.y - rel.x; i += BS) s_wstart[i] = d.lwin[rel.x + i].x;
   // Thalamic tables of the window's instance.
   if (tid < 8u) {
@@ -667,7 +715,7 @@ __global__ __launch_bounds__(BS) void k_band(DeviceNet d, uint32_t n_steps, uint
         const uint32_t nb = min(SB, total - m0);
         const uint32_t n_l = nb > wave ? (nb - wave + NW - 1u) / NW : 0u;
         uint64_t base = 0;
-        uint32_t cap = 0, rb = 0;
+        uint32_t cap = 0, rb = 0, cl = 0;
         if (lane < n_l) {
           uint32_t m = m0 + wave + NW * lane, j = 1;
 #pragma unroll
@@ -681,13 +729,14 @@ __global__ __launch_bounds__(BS) void k_band(DeviceNet d, uint32_t n_steps, uint
           const uint32_t ci = sender_class(gid);
           cap = gid - s_cf[ci] < s_cn[ci] ? s_ccap[j * 8 + ci] : 0u;
           base = s_cbase[j * 8 + ci] + uint64_t(gid - s_cf[ci]) * cap;
-          rb = uint32_t(s) + (COMP ? band_lo(j, H) : 0u);
+          rb = uint32_t(s) + (FMT != kBandPlain ? band_lo(j, H) : 0u);
+          cl = ci;
         }
-        BandWalk<COMP, UR, H, PACK> bw;
-        bw.begin(base, cap, rb, n_l, gs);
+        BandWalk<FMT, UR, H, PACK> bw;
+        bw.begin(base, cap, rb, n_l, gs, cl);
         while (bw.more()) {
           bw.load(d);
-          bw.template apply<WN>(s_ring, wb0v);
+          bw.template apply<WN>(s_ring, wb0v, s_dq, s_ds);
         }
       }
     }
@@ -776,7 +825,7 @@ __global__ __launch_bounds__(BS) void k_band(DeviceNet d, uint32_t n_steps, uint
       const uint32_t nb = min(SB, n_prev - j0);
       const uint32_t n_l = nb > wave ? (nb - wave + NW - 1u) / NW : 0u;
       uint64_t base = 0;
-      uint32_t cap = 0;
+      uint32_t cap = 0, cl = 0;
       if (lane < n_l) {
         // Senders of polling wave 0 come first, then those of wave 1.
         const uint32_t j = j0 + wave + NW * lane;
@@ -793,12 +842,13 @@ __global__ __launch_bounds__(BS) void k_band(DeviceNet d, uint32_t n_steps, uint
         const uint32_t ci = sender_class(gid);
         cap = gid - s_cf[ci] < s_cn[ci] ? s_ccap[ci] : 0u;
         base = s_cbase[ci] + uint64_t(gid - s_cf[ci]) * cap;
+        cl = ci;
       }
-      BandWalk<COMP, UR, H, PACK> bw;
-      bw.begin(base, cap, uint32_t(tsrc) + (COMP ? 1u : 0u), n_l, g0);
+      BandWalk<FMT, UR, H, PACK> bw;
+      bw.begin(base, cap, uint32_t(tsrc) + (FMT != kBandPlain ? 1u : 0u), n_l, g0, cl);
       while (bw.more()) {
         bw.load(d);
-        bw.template apply<WN>(s_ring, wb0v);
+        bw.template apply<WN>(s_ring, wb0v, s_dq, s_ds);
       }
     }
     __syncthreads();
@@ -822,18 +872,19 @@ __global__ __launch_bounds__(BS) void k_band(DeviceNet d, uint32_t n_steps, uint
         for (uint32_t k0 = 0; k0 < n; k0 += 64) {
           const uint32_t n_l = min(64u, n - k0);
           uint64_t base = 0;
-          uint32_t cap = 0;
+          uint32_t cap = 0, cl = 0;
           if (lane < n_l) {
             const uint32_t gid = hist(s, k0 + lane);
             const uint32_t ci = sender_class(gid);
             cap = gid - s_cf[ci] < s_cn[ci] ? s_ccap[j * 8 + ci] : 0u;
             base = s_cbase[j * 8 + ci] + uint64_t(gid - s_cf[ci]) * cap;
+            cl = ci;
           }
-          BandWalk<COMP, UR, H, PACK> bw;
-          bw.begin(base, cap, uint32_t(s) + (COMP ? lo_j : 0u), n_l, gj);
+          BandWalk<FMT, UR, H, PACK> bw;
+          bw.begin(base, cap, uint32_t(s) + (FMT != kBandPlain ? lo_j : 0u), n_l, gj, cl);
           while (bw.more()) {
             bw.load(d);
-            bw.template apply_flush<WN>(s_ring, W_v, ntot_v, wb0v, uint32_t(t_end));
+            bw.template apply_flush<WN>(s_ring, W_v, ntot_v, wb0v, uint32_t(t_end), s_dq, s_ds);
           }
         }
       }
@@ -887,13 +938,13 @@ __global__ __launch_bounds__(BS) void k_band(DeviceNet d, uint32_t n_steps, uint
 
 using BandFn = void (*)(DeviceNet, uint32_t, uint32_t);
 
-template <bool COMP>
+template <int FMT>
 BandFn band_fn_of(uint32_t v) {
   switch (v) {
-    case 0: return k_band<256, 320, 64, 512, COMP>;
-    case 1: return k_band<256, 512, 64, 256, COMP>;
-    case 2: return k_band<512, 1536, 16, 128, COMP>;
-    case 3: return k_band<1024, 3584, 8, 32, COMP>;
+    case 0: return k_band<256, 320, 64, 512, FMT>;
+    case 1: return k_band<256, 512, 64, 256, FMT>;
+    case 2: return k_band<512, 1536, 16, 128, FMT>;
+    case 3: return k_band<1024, 3584, 8, 32, FMT>;
     default: return nullptr;
   }
 }
@@ -904,7 +955,7 @@ const BandVariant kBandVariants[kNumBandVariants] = {
     {256, 320, 64, 512}, {256, 512, 64, 256}, {512, 1536, 16, 128}, {1024, 3584, 8, 32}};
 
 int band_max_grid(uint32_t variant) {
-  BandFn fn = band_fn_of<false>(variant);
+  BandFn fn = band_fn_of<kBandPlain>(variant);
   if (!fn) return 0;
   int per_cu = 0, dev = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(fn),
@@ -916,7 +967,9 @@ int band_max_grid(uint32_t variant) {
 }
 
 hipError_t launch_band(const DeviceNet &d, uint32_t variant, uint32_t n, hipStream_t s) {
-  BandFn fn = d.syn_format == SNN_SYN_COMPRESSED5 ? band_fn_of<true>(variant) : band_fn_of<false>(variant);
+  BandFn fn = d.syn_format == SNN_SYN_COMPRESSED5 ? band_fn_of<kBandComp>(variant)
+             : d.syn_format == SNN_SYN_DEV8      ? band_fn_of<kBandDev>(variant)
+                                                 : band_fn_of<kBandPlain>(variant);
   if (!fn || d.n_lwin == 0 || d.n_lwin > kLdsMaxGrid || d.band_h != kBandVariants[variant].h)
     return hipErrorInvalidConfiguration;
   DeviceNet dv = d;

@@ -460,24 +460,22 @@ int sample_instance(const snn_instance_cfg &cfg, uint32_t syn_format, uint32_t w
 // the segment lengths (capacities) and the placement.
 int sample_instance_banded(const snn_instance_cfg &cfg, uint32_t syn_format, uint32_t win_size,
                            uint32_t band_h, int threads, HostInstance &out, std::string &err) {
-  if (syn_format == SNN_SYN_DEV8) {
-    err = "the deviation format is stored for the LDS engine only";
-    return SNN_E_INVAL;
-  }
   std::vector<Pair> pairs;
   uint32_t n_pop[8], tmax = 0;
   int rc = prepare_instance(cfg, syn_format, threads, out, pairs, n_pop, tmax, err);
   if (rc) return rc;
   const uint64_t S = out.nsyn;
   const bool comp = syn_format == SNN_SYN_COMPRESSED5;
+  const bool dev = syn_format == SNN_SYN_DEV8;
   const uint32_t OB = band_offset_bits(band_h);
+  const uint32_t OD = band_dev_offset_bits(band_h);
   if (!OB || (band_h & (band_h - 1u)) || band_h > 64u) {
     err = "ring rows of the banded layout must be 8, 16, 32 or 64";
     return SNN_E_INVAL;
   }
   const uint32_t NB = band_count(band_h);
-  if (win_size == 0 || (comp && win_size > (1u << OB))) {
-    err = "target windows too large for the banded compressed records";
+  if (win_size == 0 || (comp && win_size > (1u << OB)) || (dev && win_size > (1u << OD))) {
+    err = "target windows too large for the banded compressed or deviation records";
     return SNN_E_RANGE;
   }
   const uint32_t n = out.n;
@@ -528,8 +526,9 @@ int sample_instance_banded(const snn_instance_cfg &cfg, uint32_t syn_format, uin
   }
 
   // Pass 2: the sender-sorted rows, generation order within a row:
-  // low word the weight (2^-8 pA, or 2^-5 pA compressed), high word
-  // receiver << 6 | delay.
+  // low word the weight (2^-8 pA, or 2^-5 pA compressed; deviation format:
+  // doubled-pair bit << 8 | the 8-bit deviation), high word receiver << 6 |
+  // delay.
   std::vector<uint64_t> tmp(S);
   std::atomic<int> bad{0};
   std::vector<std::vector<int64_t>> insum(P);
@@ -554,7 +553,17 @@ int sample_instance_banded(const snn_instance_cfg &cfg, uint32_t syn_format, uin
       const double dr = std::nearbyint(pr.mu_d + pr.sd_d * gauss(s2.v[0], s2.v[1]));
       const uint32_t d = dr < 1.0 ? 1u : (dr > double(kMaxDelay) ? uint32_t(kMaxDelay) : uint32_t(dr));
       int32_t wv, wq;
-      if (comp) {
+      if (dev) {
+        // mean + deviation * step, the deviation rounded half to even and
+        // clipped to 8 bits (as the LDS layout's deviation records).
+        const uint32_t dbl = (pr.tgt == 0 && pr.src == 2) ? 1u : 0u;
+        const int di = int(2 * pr.src + dbl);
+        const int32_t mq = out.dev_mq[di], sq = out.dev_sq[di];
+        const double q = std::nearbyint((w * 256.0 - double(mq)) / double(sq));
+        const int32_t dv = q < -127.0 ? -127 : (q > 127.0 ? 127 : int32_t(q));
+        wv = int32_t((dbl << 8) | uint32_t(uint8_t(int8_t(dv))));
+        wq = mq + dv * sq;
+      } else if (comp) {
         const double q = std::nearbyint(w * 32.0);
         if (!(q >= -32768.0 && q <= 32767.0)) {
           bad.store(2);
@@ -652,13 +661,20 @@ int sample_instance_banded(const snn_instance_cfg &cfg, uint32_t syn_format, uin
   out.tgt16.clear();
   out.w16.clear();
   out.d8.clear();
-  if (comp)
+  out.rec2.clear();
+  out.dev8.clear();
+  if (comp) {
     out.rec4.assign(run, 0);
-  else
+  } else if (dev) {
+    out.rec2.assign(run, 0);
+    out.dev8.assign(run, int8_t(-128));
+  } else {
     out.rec8.assign(run, 0);
+  }
 
   // Pass 4: placement, generation order within a segment.  Unused slots stay
-  // zero (weight 0: they add nothing).
+  // zero (weight 0: they add nothing), or hold the deviation -128, which no
+  // synapse has.
   parallel_for(P, [&](int t) {
     std::vector<uint64_t> at(nkey, 0);
     std::vector<uint32_t> stamp(nkey, ~0u);
@@ -677,6 +693,12 @@ int sample_instance_banded(const snn_instance_cfg &cfg, uint32_t syn_format, uin
           const uint32_t b = uint32_t(kk % NB);
           out.rec4[pos] = (uint32_t(uint16_t(int16_t(int32_t(uint32_t(r))))) << 16) |
                           ((d - band_lo(b, band_h)) << OB) | (post % win_size);
+        } else if (dev) {
+          const uint32_t hiw = uint32_t(r >> 32), d = hiw & 63u, post = hiw >> 6;
+          const uint32_t b = uint32_t(kk % NB), lw = uint32_t(r);
+          out.rec2[pos] = uint16_t(((lw >> 8) << 15) | ((d - band_lo(b, band_h)) << OD) |
+                                   (post % win_size));
+          out.dev8[pos] = int8_t(uint8_t(lw & 0xFFu));
         } else {
           out.rec8[pos] = r;
         }

@@ -655,8 +655,8 @@ int snn_build(const snn_config *cfg, snn_net **out) {
   if (cfg->syn_format > SNN_SYN_DEV8)
     return fail(nullptr, SNN_E_INVAL, "unknown synapse format %u", cfg->syn_format);
   if (cfg->syn_format == SNN_SYN_DEV8 && cfg->engine != SNN_ENGINE_AUTO &&
-      cfg->engine != SNN_ENGINE_LDS)
-    return fail(nullptr, SNN_E_INVAL, "the deviation format runs on the LDS engine only");
+      cfg->engine != SNN_ENGINE_LDS && cfg->engine != SNN_ENGINE_BAND)
+    return fail(nullptr, SNN_E_INVAL, "the deviation format runs on the LDS and banded engines only");
   if (cfg->engine > SNN_ENGINE_BAND)
     return fail(nullptr, SNN_E_INVAL, "unknown engine %u", cfg->engine);
   if (cfg->inst_window_neurons) {
@@ -745,8 +745,10 @@ int snn_build(const snn_config *cfg, snn_net **out) {
       h->lds_groups = plan.groups;
       break;
     }
-    if (cfg->engine != SNN_ENGINE_AUTO || cfg->syn_format == SNN_SYN_DEV8) {
-      fail(h, prc, "%s%s", cfg->syn_format == SNN_SYN_DEV8 ? "the deviation format needs the LDS engine: " : "",
+    // The deviation format has no layout for the persistent engine.
+    const bool dev_end = cfg->syn_format == SNN_SYN_DEV8 && h->engine == SNN_ENGINE_BAND;
+    if (cfg->engine != SNN_ENGINE_AUTO || dev_end) {
+      fail(h, prc, "%s%s", dev_end ? "the deviation format needs the LDS or banded engine: " : "",
            why.c_str());
       return bail(prc);
     }
@@ -1454,9 +1456,7 @@ std::vector<TuneCand> tune_candidates(const snn_config *cfg) {
     }
   };
   if (cfg->engine == SNN_ENGINE_AUTO || cfg->engine == SNN_ENGINE_LDS) family(SNN_ENGINE_LDS);
-  if ((cfg->engine == SNN_ENGINE_AUTO || cfg->engine == SNN_ENGINE_BAND) &&
-      cfg->syn_format != SNN_SYN_DEV8)
-    family(SNN_ENGINE_BAND);
+  if (cfg->engine == SNN_ENGINE_AUTO || cfg->engine == SNN_ENGINE_BAND) family(SNN_ENGINE_BAND);
   return out;
 }
 
@@ -1734,7 +1734,16 @@ int read_back(const HostInstance &x, uint32_t syn_format, snn_host_network **out
           uint32_t post, dl;
           int32_t wq;
           bool unused;
-          if (syn_format == SNN_SYN_DEV8) {   // doubled << 15 | delay << 9 | offset, deviation
+          if (syn_format == SNN_SYN_DEV8 && x.band_h) {
+            // banded: doubled << 15 | (delay - band_lo) << od | offset, deviation (-128: unused)
+            const uint32_t od = band_dev_offset_bits(x.band_h);
+            const uint32_t r = x.rec2[e2];
+            const int di = int(2 * c + (r >> 15));
+            post = w * x.win_size + (r & ((1u << od) - 1u));
+            dl = band_lo(b, x.band_h) + ((r >> od) & (x.band_h - 1u));
+            wq = x.dev_mq[di] + int32_t(x.dev8[e2]) * x.dev_sq[di];
+            unused = x.dev8[e2] == -128;
+          } else if (syn_format == SNN_SYN_DEV8) {   // doubled << 15 | delay << 9 | offset, deviation
             const uint32_t r = x.rec2[e2];
             const int di = int(2 * c + (r >> 15));
             post = (x.win_first + w) * x.win_size + (r & 511u) - x.win_origin;

@@ -77,6 +77,13 @@ SNN_HD constexpr uint32_t band_of(uint32_t d, uint32_t H) { return d <= 1 ? 0u :
 SNN_HD constexpr uint32_t band_offset_bits(uint32_t H) {
   return H >= 64 ? 10u : H >= 32 ? 11u : H >= 16 ? 12u : H >= 8 ? 13u : 0u;
 }
+// Deviation-format banded locators (Sec. 5.3: the pair's mean and the band's
+// first delay implicit): doubled-pair bit << 15 | (delay - band_lo) << OD |
+// offset in the window (OD bits), OD = 15 - log2(H); the 8-bit deviation is a
+// parallel stream, -128 marking an unused slot.
+SNN_HD constexpr uint32_t band_dev_offset_bits(uint32_t H) {
+  return band_offset_bits(H) ? band_offset_bits(H) - 1u : 0u;
+}
 
 // Per-instance table the kernels read (device memory, uniform per wave).
 struct InstDev {
@@ -170,7 +177,8 @@ int sample_instance(const snn_instance_cfg &cfg, uint32_t syn_format, uint32_t w
 // first neuron, segments per (sender, window, delay band) for a ring of
 // band_h rows; cls_cap / cls_base are indexed [(window * nband + band) * 8 +
 // class].  Plain records as above; compressed records weight << 16 | (delay -
-// band_lo) << band_offset_bits | offset in the window.
+// band_lo) << band_offset_bits | offset in the window; deviation-format
+// locators as band_dev_offset_bits describes, with the deviation stream.
 int sample_instance_banded(const snn_instance_cfg &cfg, uint32_t syn_format, uint32_t win_size,
                            uint32_t band_h, int threads, HostInstance &out, std::string &err);
 // Population sizes of an instance (for placement before sampling).

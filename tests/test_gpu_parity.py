@@ -232,7 +232,7 @@ def test_band_tiny_bit_exact(P, oracle, fmt, wmode):
 @pytest.mark.parametrize("scale,block,grid,chunk,rows", [
     (0.05, 512, 4, 37, 16), (0.05, 512, 3, 1, 16), (0.05, 1024, 2, 50, 8),
     (0.01, 1024, 1, 7, 8), (0.05, 256, 12, 3, 64), (0.05, 512, 9, 200, 16)])
-@pytest.mark.parametrize("fmt,wmode", [("plain", 0), ("compressed", 1)])
+@pytest.mark.parametrize("fmt,wmode", [("plain", 0), ("compressed", 1), ("dev8", 2)])
 def test_band_shapes(P, oracle, scale, block, grid, chunk, rows, fmt, wmode):
     """Banded engine with 16 (512-thread blocks) and 8 (1024-thread blocks)
     ring rows in LDS, horizon-based delivery (Sec. 3.4): launches of 1 to
@@ -261,9 +261,9 @@ def test_band_high_activity(P, oracle, block):
     """Banded engine under a burst (half-scale circuit, g = -2, 16 Hz
     background): steps of several hundred senders overflow the LDS sender
     history into device memory and fill the sender lists; with 64, 16 and 8
-    ring rows."""
+    ring rows (plain, compressed and deviation records)."""
     inst = P.Instance(scale=0.5, seed=7, g=-2.0, bg_rate_hz=16.0)
-    fmt, wmode = ("compressed", 1) if block == 512 else ("plain", 0)
+    fmt, wmode = {256: ("plain", 0), 512: ("compressed", 1), 1024: ("dev8", 2)}[block]
     say("band high activity", block, fmt)
     with P.Simulator(inst, syn_format=fmt, engine="band", block_size=block, chunk_steps=60) as sim:
         info = sim.info()
@@ -284,7 +284,7 @@ def test_band_batched_instances(P, oracle, block):
              P.Instance(scale=0.023, seed=12, g=-5.0, bg_rate_hz=9.0),
              P.Instance(scale=0.013, seed=13, g=-3.5, bg_rate_hz=6.5, indegree_mode=1),
              P.Instance(scale=0.002, seed=14)]
-    for fmt, wmode in [("plain", 0), ("compressed", 1)]:
+    for fmt, wmode in [("plain", 0), ("compressed", 1), ("dev8", 2)]:
         say("band batch", block, fmt)
         with P.Simulator(insts, syn_format=fmt, engine="band", block_size=block,
                          chunk_steps=90) as sim:

@@ -176,13 +176,15 @@ def test_windowed_layout_holds_the_oracle_network(P, oracle, window, fmt, wmode)
 
 
 @pytest.mark.parametrize("window,ring_rows", [(256, 64), (1000, 16), (2048, 8), (320, 32)])
-@pytest.mark.parametrize("fmt,wmode", [("plain", 0), ("compressed", 1)])
+@pytest.mark.parametrize("fmt,wmode", [("plain", 0), ("compressed", 1), ("dev8", 2)])
 def test_banded_layout_holds_the_oracle_network(P, oracle, window, ring_rows, fmt, wmode):
     """The banded engine's layout (fixed-capacity segments per sender,
     target window and delay band: delay 1, then bands of H delays from 2 on,
     Sec. 3.4) read back gives every row of the oracle's network, as a
     multiset, and nothing else; within a row, synapses come by window, then
-    by band, and every synapse sits in the band of its delay."""
+    by band, and every synapse sits in the band of its delay.  The deviation
+    format's locators keep the delay relative to its band and the offset in
+    its window, the pair's mean implicit (Sec. 5.3)."""
     scale, mode, seed = 0.04, 1, 4
     a = P.sample_network(P.Instance(scale=scale, indegree_mode=mode, seed=seed), fmt, window=window,
                          ring_rows=ring_rows)
@@ -204,14 +206,16 @@ def test_banded_layout_holds_the_oracle_network(P, oracle, window, ring_rows, fm
     assert band.max() <= (62 + ring_rows - 1) // ring_rows and band.max() >= 1
 
 
-def test_dev8_format_is_for_the_lds_layout_only(P):
-    """The deviation format (Sec. 5.3) is stored for the LDS engine: the other
-    layouts and engines refuse it instead of quantising differently."""
+def test_dev8_format_is_for_the_lds_engines_only(P):
+    """The deviation format (Sec. 5.3) is stored for the LDS and banded
+    engines: the unwindowed layout and the other engines refuse it instead of
+    quantising differently, and so do banded windows wider than its locator's
+    offset field."""
     inst = P.Instance(scale=0.01)
     with pytest.raises(P.SnnError, match="INVAL"):
         P.sample_network(inst, "dev8")
-    with pytest.raises(P.SnnError, match="INVAL"):
-        P.sample_network(inst, "dev8", window=256, ring_rows=16)
+    with pytest.raises(P.SnnError, match="RANGE"):
+        P.sample_network(inst, "dev8", window=1024, ring_rows=64)   # 9 offset bits at 64 rows
     S = P.snn
     L = P.lib()
     h = C.c_void_p()
@@ -221,10 +225,10 @@ def test_dev8_format_is_for_the_lds_layout_only(P):
     L.snn_instance_default(C.byref(ci))
     cfg.inst = C.pointer(ci)
     cfg.syn_format = S.SYN_DEV8
-    for engine in [S.ENGINE_PERSISTENT, S.ENGINE_STEPWISE, S.ENGINE_BAND]:
+    for engine in [S.ENGINE_PERSISTENT, S.ENGINE_STEPWISE]:
         cfg.engine = engine
         assert L.snn_build(C.byref(cfg), C.byref(h)) == -1   # checked before any device call
-        assert b"LDS engine only" in L.snn_last_error(None)
+        assert b"LDS and banded engines only" in L.snn_last_error(None)
         assert not h
 
 
