@@ -257,7 +257,7 @@ struct BandWalk {
   // each level is a cross-lane read whose latency the other units' reads
   // hide.  The first level compares with lane 32 for every slot.
   __device__ __forceinline__ void load_packed(const DeviceNet &d) {
-    constexpr int PG = 4;
+    constexpr int PG = 2;
     static_assert(UR % PG == 0, "units per round: a multiple of the search group");
     const uint32_t lane = __lane_id();
     const uint32_t p32 = uint32_t(__builtin_amdgcn_readlane(p_l, 32));
