@@ -364,7 +364,10 @@ __global__ __launch_bounds__(BS) void k_band(DeviceNet d, uint32_t n_steps, uint
   constexpr uint32_t NZH = NZ / 2;             // windows polled by one wave
   constexpr uint32_t RC = 640;                 // raster staging entries
   constexpr uint32_t SB = 64 * NW;             // senders resolved per round
-  constexpr int UR = BS >= 1024 ? 4 : (BS == 512 ? 16 : 8);   // loads in flight per lane
+  // Loads in flight per lane.  The 1,024-thread variant keeps 12 although
+  // its registers then spill part of them to scratch: fewer in flight leave
+  // it waiting on the memory latency (measured: 4 and 8 slower, 16 too).
+  constexpr int UR = BS >= 1024 ? 12 : (BS == 512 ? 16 : 8);
   constexpr bool PACK = BS == 512;             // packed walk (the variant of the widest bands)
   static_assert(Q0 >= 128, "waves 0 and 1 own no quad");
   static_assert(NSLOT > LOMAX, "the history must reach the last slow band");
