@@ -203,8 +203,11 @@ int snn_step_n(snn_net *h, uint64_t n_steps);
  * The per-call state of the step loop (control words, flag words, sender
  * lists and the sender history) lives in a static 32 MiB device array per
  * GPU, cleared at the start of every call; networks needing more return
- * SNN_E_RANGE (the LDS engine fits up to about 2 million neurons, the
- * banded engine about 120,000).  Calls on one GPU must not overlap: they
+ * SNN_E_RANGE (the LDS engine fits up to about 2 million neurons; the
+ * banded engine, whose sender history takes 272 bytes per neuron plus 48 KiB
+ * per block below 1,024 threads, about 77,000 at 256 threads and 304-neuron
+ * windows, 107,000 at 512 threads, 123,000 at 1,024).  Calls on one GPU must
+ * not overlap: they
  * share that array.  State, counters and snn_read_state are as after
  * snn_step_n; the spikes of this call are not in the handle's raster.
  * Errors: SNN_E_INVAL, SNN_E_RANGE, SNN_E_HIP, SNN_E_DEVICE.
