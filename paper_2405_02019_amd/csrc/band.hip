@@ -15,9 +15,10 @@
 // H delays per spike every H steps in the same way; here the first band is
 // cut to the single delay the next decision depends on.
 //
-// The sender ids of past steps are kept per block (an LDS history of HC ids
-// per step, the rest in device memory, written identically by every block of
-// the instance).  Between launches the 64-row ring in device memory is
+// The sender ids of past steps are kept per block: an LDS history of HC ids
+// per step, then (below 1,024 threads) 192 more in device memory private to
+// the block, the rest in device memory shared by the instance's blocks, which
+// all write the same ids there.  Between launches the 64-row ring in device memory is
 // complete: a launch loads rows [t0, t0 + H) and pulls rows t0 + H .. t0 + 63
 // as they enter the horizon, and at its end delivers every slow band still
 // pending -- into LDS rows inside the horizon, with device atomics beyond it
