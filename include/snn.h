@@ -410,6 +410,23 @@ int snn_sample_network_bands(const snn_instance_cfg *inst, uint32_t syn_format, 
                              uint32_t ring_rows, int32_t host_threads, snn_host_network **out);
 void snn_free_network(snn_host_network *net);
 
+/*
+ * snn_balanced_windows -- host only: the per-instance window lengths that
+ * snn_build_tuned tries for several instances (Sec. 3.6's destination
+ * classes sized by load).  Instance k (n_neurons[k] neurons, load[k]
+ * synaptic events per neuron and step, >= 0) gets windows of about T /
+ * load[k] neurons, a multiple of 4 in [4, max_window] (max_window for a
+ * silent instance), for the smallest per-block load T whose windows -- the
+ * instance's quads cut into windows of at most that many neurons -- number
+ * at most max_blocks in all.  window_out (caller-owned, n_instances entries)
+ * receives the lengths.
+ * Errors: SNN_E_INVAL (NULL array, no instances, a negative or non-finite
+ * load, max_window not a positive multiple of 4); SNN_E_RANGE when even
+ * max_window-neuron windows exceed max_blocks.
+ */
+int snn_balanced_windows(uint32_t n_instances, const uint32_t *n_neurons, const double *load,
+                         uint32_t max_window, uint32_t max_blocks, uint32_t *window_out);
+
 #ifdef __cplusplus
 }
 #endif

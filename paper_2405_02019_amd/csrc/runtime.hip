@@ -2,6 +2,7 @@
 // (caller allocator or hipMalloc), the HIP stream, captured step chunks, raster
 // drains and state readback.
 #include <algorithm>
+#include <cmath>
 #include <chrono>
 #include <cstdarg>
 #include <cstdio>
@@ -1814,6 +1815,28 @@ int snn_sample_network_windows(const snn_instance_cfg *inst, uint32_t syn_format
   int rc = sample_instance(*inst, syn_format, wsize, 0, window != 0, host_threads, x, e);
   if (rc) return fail(nullptr, rc, "%s", e.c_str());
   return read_back(x, syn_format, out);
+}
+
+int snn_balanced_windows(uint32_t n_instances, const uint32_t *n_neurons, const double *load,
+                         uint32_t max_window, uint32_t max_blocks, uint32_t *window_out) {
+  if (!n_instances || !n_neurons || !load || !window_out)
+    return fail(nullptr, SNN_E_INVAL, "NULL array or no instances");
+  if (max_window < 4 || max_window % 4)
+    return fail(nullptr, SNN_E_INVAL, "max_window must be a positive multiple of 4");
+  std::vector<InstMeta> im(n_instances);
+  std::vector<double> w(n_instances);
+  for (uint32_t k = 0; k < n_instances; ++k) {
+    if (!(load[k] >= 0.0) || !std::isfinite(load[k]))
+      return fail(nullptr, SNN_E_INVAL, "instance %u: load must be finite and >= 0", k);
+    im[k].n = n_neurons[k];
+    w[k] = load[k];
+  }
+  std::vector<uint32_t> L;
+  if (!balanced_lengths(im, w, max_window, max_blocks, L))
+    return fail(nullptr, SNN_E_RANGE, "%u-neuron windows need more than %u blocks", max_window,
+                max_blocks);
+  std::copy(L.begin(), L.end(), window_out);
+  return SNN_OK;
 }
 
 int snn_sample_network_bands(const snn_instance_cfg *inst, uint32_t syn_format, uint32_t window,

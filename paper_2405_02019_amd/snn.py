@@ -117,6 +117,8 @@ SIGNATURES = {
     "snn_sample_network_bands": (C.c_int, [C.POINTER(_Inst), C.c_uint32, C.c_uint32, C.c_uint32,
                                            C.c_int32, C.POINTER(C.POINTER(_HostNet))]),
     "snn_free_network": (None, [C.POINTER(_HostNet)]),
+    "snn_balanced_windows": (C.c_int, [C.c_uint32, C.POINTER(C.c_uint32), C.POINTER(C.c_double),
+                                       C.c_uint32, C.c_uint32, C.POINTER(C.c_uint32)]),
 }
 
 _lib = None
@@ -345,6 +347,18 @@ class Simulator:
         inf = _Info()
         _check(lib().snn_get_info(self.h, C.byref(inf)), self.h)
         return {f: getattr(inf, f) for f, _ in _Info._fields_}
+
+
+def balanced_windows(n_neurons, load, max_window, max_blocks):
+    """Per-instance window lengths sized by load (snn_balanced_windows, host
+    only): instance k of n_neurons[k] neurons and load[k] synaptic events
+    per neuron and step."""
+    n = len(n_neurons)
+    nn = (C.c_uint32 * n)(*[int(x) for x in n_neurons])
+    ld = (C.c_double * n)(*[float(x) for x in load])
+    out = (C.c_uint32 * n)()
+    _check(lib().snn_balanced_windows(n, nn, ld, int(max_window), int(max_blocks), out))
+    return [int(x) for x in out]
 
 
 def sample_network(instance: Instance, syn_format="plain", host_threads=0, window=0, ring_rows=0):

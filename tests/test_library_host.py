@@ -267,3 +267,57 @@ def test_sampler_error_paths(P):
         P.sample_network(P.Instance(scale=0.01, conn=np.full(64, 1.5)))
     with pytest.raises(P.SnnError, match="INVAL"):
         P.sample_network(P.Instance(scale=0.01, bg_const_T=65))
+
+
+def _windows(n, L):
+    """Windows of an instance of n neurons at window length L (balanced
+    windows of whole quads)."""
+    nq = (n + 3) // 4
+    nw = -(-nq // (L // 4))
+    wq = -(-nq // nw)
+    return -(-nq // wq)
+
+
+def test_balanced_windows_reach_the_brute_force_optimum(P):
+    """Windows sized by load (snn_balanced_windows; Sec. 3.6's destination
+    classes, each block delivering about as many events): over every
+    combination of window lengths (multiples of 4 up to the capacity) whose
+    windows fit the blocks, the smallest possible maximum per-block load
+    max_k load_k * L_k is what the bisection reaches, within its
+    resolution."""
+    import itertools
+    rng = np.random.default_rng(3)
+    for case in range(12):
+        k = int(rng.integers(2, 4))
+        n = [int(x) for x in rng.integers(20, 400, k)]
+        load = [float(x) for x in rng.uniform(0.2, 3.0, k)]
+        wn = int(rng.choice([32, 64, 96]))
+        fewest = sum(_windows(nk, wn) for nk in n)
+        blocks = fewest + int(rng.integers(0, 12))
+        L = P.balanced_windows(n, load, wn, blocks)
+        assert all(4 <= x <= wn and x % 4 == 0 for x in L)
+        assert sum(_windows(nk, x) for nk, x in zip(n, L)) <= blocks
+        best = min(max(w * x for w, x in zip(load, combo))
+                   for combo in itertools.product(range(4, wn + 1, 4), repeat=k)
+                   if sum(_windows(nk, x) for nk, x in zip(n, combo)) <= blocks)
+        got = max(w * x for w, x in zip(load, L))
+        assert got <= best * (1 + 1e-9), (case, n, load, wn, blocks, L, got, best)
+
+
+def test_balanced_windows_special_cases(P):
+    """Equal instances get equal windows; an instance with twice the load
+    gets about half the window; a silent one the full capacity; the
+    capacity itself when the blocks allow nothing shorter; errors for
+    windows that cannot fit and for bad arguments."""
+    assert P.balanced_windows([1000, 1000], [1.0, 1.0], 512, 8) == [252, 252]
+    a, b = P.balanced_windows([1000, 1000], [1.0, 2.0], 512, 12)
+    assert abs(a / b - 2.0) < 0.1
+    assert P.balanced_windows([1000, 1000], [0.0, 1.0], 512, 64)[0] == 512
+    assert P.balanced_windows([1000], [1.0], 512, 2) == [500]
+    assert P.balanced_windows([1024], [1.0], 512, 2) == [512]
+    with pytest.raises(P.SnnError, match="RANGE"):
+        P.balanced_windows([1024], [1.0], 512, 1)
+    with pytest.raises(P.SnnError, match="INVAL"):
+        P.balanced_windows([1000], [-1.0], 512, 8)
+    with pytest.raises(P.SnnError, match="INVAL"):
+        P.balanced_windows([1000], [1.0], 510, 8)
